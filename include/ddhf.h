@@ -1,0 +1,226 @@
+/*
+ * ddhf.h -- C ABI of the DDHF hot path on AMD Instinct MI355X (gfx950).
+ *
+ * DDHF detects drone rotors in event-camera streams: per-pixel non-uniform DFT
+ * power spectra of the event polarities (Sec. 3.3, Eq. 6), a spectral-flatness
+ * gate (Eq. 7), a median-normalised harmonic comb score (Eq. 8-11), and a
+ * mask -> 8-connected components -> boxes -> merge step (Sec. 3.5, Eq. 12).
+ *
+ * Conventions shared by every call:
+ *  - Array pointers are DEVICE pointers unless the name ends in _host.
+ *    Scalars and the small parameter structs (grid, params, launch) are read
+ *    from host memory during the call and may be reused afterwards.
+ *  - The caller owns all memory.  Calls that need scratch take a workspace
+ *    (ws, ws_bytes) whose minimum size the matching *_workspace_size call
+ *    returns; hot calls never allocate.
+ *  - Every call is stream ordered on `stream` (a hipStream_t passed as void*,
+ *    NULL = the default stream) and returns without synchronising.
+ *  - Return value: DDHF_OK, or an error status that is detected on the host
+ *    before anything is launched (arguments) or after a launch (HIP error).
+ *    Data-dependent conditions (events outside the window or sensor, too many
+ *    boxes) are counted on the device, never fatal.
+ *  - Thread safety: calls keep no global state and are re-entrant; a workspace
+ *    must not be shared by calls that may run concurrently.
+ */
+#ifndef DDHF_H
+#define DDHF_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status ------------------------------------------------------------ */
+enum {
+    DDHF_OK = 0,
+    DDHF_EINVAL = 1,   /* null pointer, size out of range, grid that could overflow */
+    DDHF_ENOSPACE = 2, /* workspace smaller than *_workspace_size reported */
+    DDHF_EHIP = 3,     /* a HIP launch or runtime call failed */
+    DDHF_ETRUNC = 4    /* reserved: results truncated (reported through counts) */
+};
+
+/* Text for a status code (static storage). */
+const char* ddhf_status_string(int status);
+
+/* ---- parameter structs --------------------------------------------------- */
+
+/* Frequency grid.  Bin j < K has the integer frequency numerator
+ * f_j = f0 + j * df (f0 >= 0, df > 0).  For an event at integer time t_rel
+ * (microseconds since the window start) the phase is 2 pi r / Q with
+ * r = (f_j * t_rel) mod Q computed exactly in integers:
+ *   mode 0 (DDHF_GRID_HZ):    f in milli-Hertz, Q = 1e9;
+ *   mode 1 (DDHF_GRID_MODES): f = integer mode k, Q = T_w_us: Eq. 6 with the
+ *     window's timestamps mapped linearly onto [-pi, pi) and integer modes
+ *     k = 0..K-1 (Sec. 3.3 and 3.5); the -pi offset only rotates F_k.
+ * Requires f_max * 2^32 < 2^63 and Q <= 2^30. */
+enum { DDHF_GRID_HZ = 0, DDHF_GRID_MODES = 1 };
+typedef struct {
+    int64_t f0;
+    int64_t df;
+    int32_t K;
+    int32_t mode;
+    int64_t T_w_us;
+} ddhf_grid_t;
+
+/* Detection hyperparameters, Table 2 symbols: tau_sf (Eq. 7 gate), tau_comb
+ * (Eq. 11), alpha (Eq. 12), M harmonics and dk half-width (Eq. 8), h_min
+ * (minimum in-band harmonics, Eq. 8), n_min (minimum events per pixel,
+ * Sec. 3.5), a_min (minimum bounding-box area in pixels, Sec. 3.5).  eps_rel
+ * floors log(P) in Eq. 7 and a zero median in Eq. 10 at eps_rel * mean(P). */
+typedef struct {
+    float tau_sf;
+    float tau_comb;
+    float alpha;
+    float eps_rel;
+    int32_t M;
+    int32_t dk;
+    int32_t h_min;
+    int32_t n_min;
+    int32_t a_min;
+    int32_t reserved;
+} ddhf_params_t;
+
+/* A detection: inclusive bounding box, number of mask pixels, and the
+ * dominant frequency (Hz) of its representative pixel (the member with the
+ * highest comb score, lowest pixel index on ties). */
+typedef struct {
+    int32_t x0, y0, x1, y1;
+    int32_t n_px;
+    float f_dom_hz;
+    int32_t rep_pixel;
+    float rep_snr;
+} ddhf_box_t;
+
+/* Device-side counters of ddhf_build_pixel_index (each event is counted in
+ * the first category it fails: window, then sensor, then polarity). */
+typedef struct {
+    int64_t n_in;
+    int64_t n_kept;
+    int64_t out_of_window;
+    int64_t out_of_sensor;
+    int64_t bad_polarity;
+    int64_t time_unsorted; /* number of i >= 1 with t[i] < t[i-1] */
+} ddhf_counters_t;
+
+/* NDFT launch shape.  NULL selects the plain launch: one wavefront per
+ * (active pixel, bin tile), lanes owning bins, events staged in LDS.
+ *   kernel:        0 = VALU (lanes own bins, phasor recurrence per lane),
+ *                  1 = MFMA (factorised: F[J b + s] = sum_e U[b,e] V[e,s]
+ *                      as FP32 matrix-core products, J = 32);
+ *   bins_per_lane: VALU bins per lane per tile (8, 16, 32 or 64);
+ *   split_events:  pixels with more events than this are split into event
+ *                  chunks whose partial spectra are summed in a fixed order
+ *                  (0 = never split);
+ *   persistent:    1 = a fixed grid of waves pulls (pixel, tile, chunk) units,
+ *                  heaviest first, from a device queue;
+ *   grid_waves:    persistent grid size in waves (0 = auto).
+ * ddhf_autotune fills this struct. */
+enum { DDHF_KERNEL_VALU = 0, DDHF_KERNEL_MFMA = 1 };
+typedef struct {
+    int32_t kernel;
+    int32_t bins_per_lane;
+    int32_t split_events;
+    int32_t persistent;
+    int32_t grid_waves;
+    int32_t reserved;
+} ddhf_launch_t;
+
+/* ---- 1. events -> pixel-sorted CSR (Sec. 3.5 "Event Processing") -------- */
+
+/* Flag: the caller guarantees t_us is non-decreasing, so only the pixel key
+ * is sorted (a stable sort then yields the (pixel, time, index) order). */
+#define DDHF_INDEX_TIME_SORTED 1
+
+int ddhf_build_pixel_index_workspace_size(int64_t n, int32_t W, int32_t H, int64_t T_w_us,
+                                          int32_t flags, size_t* bytes);
+
+/* Sorts the window's events by (pixel, time, input index) into CSR.
+ * In:  x, y [n] u16 pixel coordinates; p [n] i8 polarity in {0,1} or {-1,+1}
+ *      (p > 0 -> +1, else -1; values outside [-1, 1] are dropped); t_us [n]
+ *      i64 timestamps; w [n] optional f32 per-event weight (NULL = 1).
+ *      Events with t outside [t0_us, t0_us + T_w_us), x >= W or y >= H are
+ *      dropped.  n may be 0; W * H must be < 2^31 - 1; T_w_us < 2^31.
+ * Out: row_ptr [W*H + 1]: events of pixel q = y*W + x are k in
+ *      [row_ptr[q], row_ptr[q+1]); row_ptr[W*H] = number kept.
+ *      t_rel [n] u32 = t - t0_us, a [n] f32 = polarity * weight, perm [n] i32
+ *      = input index, all in CSR order (entries >= n_kept are unspecified).
+ *      counters: device ddhf_counters_t (may be NULL).
+ * Bit-exact and deterministic. */
+int ddhf_build_pixel_index(const uint16_t* x, const uint16_t* y, const int8_t* p,
+                           const int64_t* t_us, const float* w, int64_t n, int32_t W, int32_t H,
+                           int64_t t0_us, int64_t T_w_us, int32_t flags, int32_t* row_ptr,
+                           uint32_t* t_rel, float* a, int32_t* perm, ddhf_counters_t* counters,
+                           void* ws, size_t ws_bytes, void* stream);
+
+/* ---- 2. active pixels (Sec. 3.5: pixels with fewer than n_min events are
+ *         discarded) ----------------------------------------------------- */
+
+int ddhf_active_pixels_workspace_size(int32_t n_pix, size_t* bytes);
+
+/* active [n_pix] receives the pixels with row_ptr[q+1] - row_ptr[q] >= n_min,
+ * ascending by pixel index, or (order_by_cost != 0) grouped by descending
+ * floor(log2(count)) and ascending pixel index inside a group (the order the
+ * persistent NDFT wants).  *n_active (device i32) receives the count. */
+int ddhf_active_pixels(const int32_t* row_ptr, int32_t n_pix, int32_t n_min,
+                       int32_t order_by_cost, int32_t* active, int32_t* n_active, void* ws,
+                       size_t ws_bytes, void* stream);
+
+/* ---- 3. per-pixel NDFT power (Eq. 6) ------------------------------------- */
+
+int ddhf_ndft_workspace_size(int32_t n_active, int64_t n_events, const ddhf_grid_t* grid,
+                             const ddhf_launch_t* launch, size_t* bytes);
+
+/* power [n_active * K] f32 row-major: power[u*K + j] = |F_u(f_j)|^2 with
+ * F_u(f) = sum over the events of pixel active[u] of a_e exp(i 2 pi r / Q),
+ * r = (f t_rel) mod Q (exact integer residue), FP32 sin/cos and accumulation.
+ * Inputs are the outputs of calls 1 and 2 (n_active is the host copy of the
+ * count).  launch may be NULL (plain).  Error against FP64:
+ * |P - P64| <= 1e-4 max(P64, sum_e a_e^2) per pixel and bin. */
+int ddhf_ndft_power(const int32_t* row_ptr, const uint32_t* t_rel, const float* a,
+                    const int32_t* active, int32_t n_active, const ddhf_grid_t* grid, float* power,
+                    const ddhf_launch_t* launch, void* ws, size_t ws_bytes, void* stream);
+
+/* ---- 4. spectral flatness + harmonic comb (Eq. 7-11) --------------------- */
+
+/* For each row u of power [n_active * K]:
+ *   sf[u]   = exp(mean_j log max(P_j, eps mean P)) / mean P   (1 if P == 0);
+ *   for candidate bins i: harmonic centres c_m = ((m-1) f0 + m i df) / df
+ *   (rounded half up), windows [c_m - dk, c_m + dk], M_valid = in-band prefix
+ *   of m = 1..M, admissible iff M_valid >= h_min; N = mean of window maxima;
+ *   baseline = lower median (rank floor((n-1)/2) by (value, bin)) of the bins
+ *   outside every window, floored at eps mean P; SNR = N / baseline;
+ *   snr_best[u] = max SNR (0 if none admissible), bin_best[u] = its bin
+ *   (lowest on ties; -1 if none).
+ * snr_all [n_active * K] (nullable) receives every candidate's SNR (0 where
+ * not admissible).  Needs M <= 32, 0 <= dk <= 16, h_min >= 1. */
+int ddhf_comb_score(const float* power, int32_t n_active, const ddhf_grid_t* grid,
+                    const ddhf_params_t* prm, float* sf, float* snr_best, int32_t* bin_best,
+                    float* snr_all, void* stream);
+
+/* ---- 5. mask, components, boxes, merge (Sec. 3.5, Eq. 12) ---------------- */
+
+#define DDHF_DETECT_MAX_CANDIDATES 1024
+
+int ddhf_detect_workspace_size(int32_t W, int32_t H, size_t* bytes);
+
+/* mask [W*H] u8 = (count >= n_min) and (sf <= tau_sf) and (snr >= tau_comb);
+ * labels [W*H] i32 = smallest pixel index of the pixel's 8-connected mask
+ * component, -1 off the mask; boxes [max_boxes]: components whose bounding
+ * box area w*h >= a_min, merged while two centres are closer than alpha times
+ * the largest side of the pair (Eq. 12, repeated to a fixed point), sorted by
+ * (y0, x0, y1, x1, n_px, rep_pixel).  n_boxes [2] (device i32): [0] = number
+ * of final boxes (may exceed max_boxes: only max_boxes are written),
+ * [1] = components dropped because more than DDHF_DETECT_MAX_CANDIDATES
+ * passed the area filter. */
+int ddhf_detect(const int32_t* active, const int32_t* row_ptr, const float* sf,
+                const float* snr_best, const int32_t* bin_best, int32_t n_active, int32_t W,
+                int32_t H, const ddhf_grid_t* grid, const ddhf_params_t* prm, uint8_t* mask,
+                int32_t* labels, ddhf_box_t* boxes, int32_t max_boxes, int32_t* n_boxes, void* ws,
+                size_t ws_bytes, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* DDHF_H */

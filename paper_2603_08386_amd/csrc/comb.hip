@@ -1,0 +1,380 @@
+// Spectral flatness (Eq. 7) and median-normalised harmonic comb (Eq. 8-11).
+//
+// One workgroup of 256 threads per active pixel; the pixel's spectrum lives
+// in LDS.  The expensive part of Eq. 10 is the median of the bins outside a
+// candidate's harmonic windows, for every candidate.  The windows remove at
+// most Hmax = M (2 dk + 1) bins, so every candidate's lower median has a full-
+// spectrum rank inside the band [b_lo, b_hi] = [floor((K - Hmax - 1) / 2),
+// floor((K - 1) / 2) + Hmax].  The kernel finds that band once per pixel with
+// an exact two-level radix select on the FP32 bit patterns (monotone for
+// P >= 0; ties ordered by bin), marks every bin as below / inside / above the
+// band, and builds prefix counts of "below" and "inside" bins.  A candidate
+// then needs O(M) LDS reads: with q0 = r + #(window bins below the band), the
+// complement median sits at the smallest full rank q with
+// q = r + #(window bins of rank <= q), reached by a short fixed-point
+// iteration over the (rare) window bins that fall inside the band.
+#include "ddhf_internal.h"
+
+namespace ddhf {
+
+constexpr int kCombThreads = 256;
+constexpr uint16_t kBelow = 0xFFFF;
+constexpr uint16_t kAbove = 0xFFFE;
+constexpr int kHistBins = 2048;
+
+struct CombArgs {
+    int32_t K, M, dk, h_min;
+    int64_t f0, df;
+    int64_t g;        // f0 / df when df divides f0, else -1
+    float eps;
+    int32_t b_lo, b_hi;
+    int32_t kpad;     // K rounded up to a multiple of 4
+};
+
+__device__ __forceinline__ double block_sum_d(double v, double* red) {
+    v = wave_sum(v);
+    const int w = threadIdx.x / kWave;
+    __syncthreads();
+    if (__lane_id() == 0) red[w] = v;
+    __syncthreads();
+    double t = 0.0;
+#pragma unroll
+    for (int k = 0; k < kCombThreads / kWave; ++k) t += red[k];
+    return t;
+}
+
+// Finds, for target ranks lo and hi, the histogram bucket containing each and
+// the number of elements in the buckets before it (cum + base offsets).
+__device__ __forceinline__ void hist_locate(const uint32_t* h, uint32_t base, int32_t tgt,
+                                            int* out_bucket, uint32_t* out_before,
+                                            uint32_t* scratch) {
+    // thread t owns buckets [8t, 8t + 8)
+    const int tid = threadIdx.x;
+    uint32_t c[8];
+    uint32_t s = 0;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) { c[i] = h[tid * 8 + i]; s += c[i]; }
+    const uint32_t incl = wave_incl_scan(s);
+    const int w = tid / kWave;
+    __syncthreads();
+    if (__lane_id() == kWave - 1) scratch[w] = incl;
+    __syncthreads();
+    uint32_t off = base;
+    for (int k = 0; k < w; ++k) off += scratch[k];
+    uint32_t run = off + incl - s;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+        if ((int64_t)run <= tgt && tgt < (int64_t)(run + c[i])) {
+            *out_bucket = tid * 8 + i;
+            *out_before = run;
+        }
+        run += c[i];
+    }
+}
+
+__global__ __launch_bounds__(kCombThreads) void k_comb(const float* __restrict__ power,
+                                                       int32_t n_active, CombArgs ca,
+                                                       float* __restrict__ sf_out,
+                                                       float* __restrict__ snr_out,
+                                                       int32_t* __restrict__ bin_out,
+                                                       float* __restrict__ snr_all) {
+    extern __shared__ __align__(16) char smem[];
+    const int K = ca.K;
+    float* sP = (float*)smem;                                  // [kpad]
+    uint16_t* sRk = (uint16_t*)(sP + ca.kpad);                 // [kpad]
+    uint16_t* sList = sRk + ca.kpad;                           // [kpad]
+    uint32_t* sHist = (uint32_t*)(sList + ca.kpad);            // [max(2 * 2048, kpad + 4)]
+    const int hist_words = (2 * kHistBins > ca.kpad + 4) ? 2 * kHistBins : ca.kpad + 4;
+    float* sBand = (float*)(sHist + hist_words);               // [b_hi - b_lo + 1]
+    __shared__ double red[kCombThreads / kWave];
+    __shared__ uint32_t scr[kCombThreads / kWave];
+    __shared__ int s_b1lo, s_b1hi, s_b2lo, s_b2hi;
+    __shared__ uint32_t s_bef1lo, s_bef1hi, s_beflo, s_befhi, s_nlist;
+    __shared__ float s_best[kCombThreads / kWave];
+    __shared__ int s_bi[kCombThreads / kWave];
+
+    const int tid = threadIdx.x;
+    const int32_t u = blockIdx.x;
+    if (u >= n_active) return;
+    const float* row = power + (int64_t)u * K;
+    if (tid == 0) {
+        s_b1lo = s_b1hi = s_b2lo = s_b2hi = 0;
+        s_bef1lo = s_bef1hi = s_beflo = s_befhi = 0;
+    }
+
+    // ---- load and mean ---------------------------------------------------
+    double sum = 0.0;
+    for (int k = tid; k < K; k += kCombThreads) {
+        const float v = row[k];
+        sP[k] = v;
+        sum += (double)v;
+    }
+    sum = block_sum_d(sum, red);
+    const double mean = sum / (double)K;
+    const float floor_v = (float)(ca.eps * mean);
+
+    // ---- spectral flatness (Eq. 7) ---------------------------------------
+    double sl = 0.0;
+    if (mean > 0.0) {
+        for (int k = tid; k < K; k += kCombThreads) {
+            const float v = sP[k] > floor_v ? sP[k] : floor_v;
+            sl += (double)__log2f(v);
+        }
+    }
+    sl = block_sum_d(sl, red);
+    if (tid == 0) sf_out[u] = mean > 0.0 ? (float)exp2(sl / (double)K - log2(mean)) : 1.0f;
+
+    // ---- radix select of the rank band -----------------------------------
+    for (int i = tid; i < 2 * kHistBins; i += kCombThreads) sHist[i] = 0;
+    __syncthreads();
+    for (int k = tid; k < K; k += kCombThreads)
+        atomicAdd(&sHist[(__float_as_uint(sP[k]) >> 20) & 0x7FF], 1u);
+    __syncthreads();
+    {
+        int bl = -1, bh = -1;
+        uint32_t fl = 0, fh = 0;
+        hist_locate(sHist, 0, ca.b_lo, &bl, &fl, scr);
+        if (bl >= 0) { s_b1lo = bl; s_bef1lo = fl; }
+        __syncthreads();
+        hist_locate(sHist, 0, ca.b_hi, &bh, &fh, scr);
+        if (bh >= 0) { s_b1hi = bh; s_bef1hi = fh; }
+    }
+    __syncthreads();
+    const int b1lo = s_b1lo, b1hi = s_b1hi;
+    uint32_t* hlo = sHist;
+    uint32_t* hhi = sHist + kHistBins;
+    for (int i = tid; i < 2 * kHistBins; i += kCombThreads) sHist[i] = 0;
+    __syncthreads();
+    for (int k = tid; k < K; k += kCombThreads) {
+        const uint32_t b = __float_as_uint(sP[k]);
+        const int d1 = (b >> 20) & 0x7FF;
+        const int d2 = (b >> 9) & 0x7FF;
+        if (d1 == b1lo) atomicAdd(&hlo[d2], 1u);
+        if (d1 == b1hi) atomicAdd(&hhi[d2], 1u);
+    }
+    __syncthreads();
+    {
+        int bl = -1, bh = -1;
+        uint32_t fl = 0, fh = 0;
+        hist_locate(hlo, s_bef1lo, ca.b_lo, &bl, &fl, scr);
+        if (bl >= 0) { s_b2lo = bl; s_beflo = fl; }
+        __syncthreads();
+        hist_locate(hhi, s_bef1hi, ca.b_hi, &bh, &fh, scr);
+        if (bh >= 0) { s_b2hi = bh; s_befhi = fh; }
+        if (tid == 0) s_nlist = 0;
+    }
+    __syncthreads();
+    const uint32_t key_lo = ((uint32_t)b1lo << 11) | (uint32_t)s_b2lo;
+    const uint32_t key_hi = ((uint32_t)b1hi << 11) | (uint32_t)s_b2hi;
+    const uint32_t below_base = s_beflo;  // elements with 22-bit key < key_lo
+    for (int k = tid; k < K; k += kCombThreads) {
+        const uint32_t kk = __float_as_uint(sP[k]) >> 9;
+        if (kk < key_lo) {
+            sRk[k] = kBelow;
+        } else if (kk > key_hi) {
+            sRk[k] = kAbove;
+        } else {
+            const uint32_t pos = atomicAdd(&s_nlist, 1u);
+            sList[pos] = (uint16_t)k;
+        }
+    }
+    __syncthreads();
+    const int nL = (int)s_nlist;
+    for (int i = tid; i < nL; i += kCombThreads) {
+        const int ki = sList[i];
+        const float vi = sP[ki];
+        uint32_t r = 0;
+        for (int j = 0; j < nL; ++j) {
+            const int kj = sList[j];
+            const float vj = sP[kj];
+            r += (vj < vi || (vj == vi && kj < ki)) ? 1u : 0u;
+        }
+        const int full = (int)(below_base + r);
+        if (full < ca.b_lo) {
+            sRk[ki] = kBelow;
+        } else if (full > ca.b_hi) {
+            sRk[ki] = kAbove;
+        } else {
+            sRk[ki] = (uint16_t)(full - ca.b_lo);
+            sBand[full - ca.b_lo] = vi;
+        }
+    }
+    __syncthreads();
+
+    // ---- prefix counts: low 16 bits = #below, high 16 bits = #inside -------
+    uint32_t* cnt = sHist;  // [K + 1]
+    {
+        const int seg = (K + kCombThreads - 1) / kCombThreads;
+        const int k0 = tid * seg;
+        uint32_t s = 0;
+        for (int k = k0; k < k0 + seg && k < K; ++k) {
+            const uint16_t r = sRk[k];
+            s += r == kBelow ? 1u : (r == kAbove ? 0u : 0x10000u);
+        }
+        const uint32_t incl = wave_incl_scan(s);
+        const int w = tid / kWave;
+        if (__lane_id() == kWave - 1) scr[w] = incl;
+        __syncthreads();
+        uint32_t run = incl - s;
+        for (int q = 0; q < w; ++q) run += scr[q];
+        for (int k = k0; k < k0 + seg && k < K; ++k) {
+            cnt[k] = run;
+            const uint16_t r = sRk[k];
+            run += r == kBelow ? 1u : (r == kAbove ? 0u : 0x10000u);
+        }
+        if (k0 < K && k0 + seg >= K) cnt[K] = run;
+        if (K == 0 && tid == 0) cnt[0] = 0;
+    }
+    __syncthreads();
+
+    // ---- candidates (Eq. 8-11) -------------------------------------------
+    const float fden_floor = (float)(ca.eps * mean);
+    const int hmax = ca.M * (2 * ca.dk + 1);
+    float best = 0.0f;
+    int best_i = -1;
+    for (int i = tid; i < K; i += kCombThreads) {
+        // harmonic centre of window m (1-based), rounded half up
+        auto centre = [&](int m) -> int64_t {
+            if (ca.g >= 0) return (int64_t)(m - 1) * ca.g + (int64_t)m * i;
+            const double num = (double)(m - 1) * (double)ca.f0 + (double)m * (double)i * (double)ca.df;
+            return (int64_t)floor(num / (double)ca.df + 0.5);
+        };
+        int mv = 0;
+        for (int m = 1; m <= ca.M; ++m) {
+            const int64_t cm = centre(m);
+            if (cm - ca.dk < 0 || cm + ca.dk > K - 1) break;
+            mv = m;
+        }
+        float snr = 0.0f;
+        if (mv >= ca.h_min && mv > 0) {
+            float smax = 0.0f;
+            int hsize = 0;
+            uint32_t below = 0, inb = 0;
+            int prev_hi = -1;
+            for (int m = 1; m <= mv; ++m) {
+                const int cm = (int)centre(m);
+                float mx = sP[cm - ca.dk];
+                for (int k = cm - ca.dk + 1; k <= cm + ca.dk; ++k) mx = fmaxf(mx, sP[k]);
+                smax += mx;
+                const int lo = (cm - ca.dk) > prev_hi + 1 ? (cm - ca.dk) : prev_hi + 1;
+                const int hi = cm + ca.dk;
+                if (lo <= hi) {
+                    hsize += hi - lo + 1;
+                    const uint32_t d = cnt[hi + 1] - cnt[lo];
+                    below += d & 0xFFFFu;
+                    inb += d >> 16;
+                }
+                prev_hi = hi;
+            }
+            const float N = smax / (float)mv;
+            const int nc = K - hsize;
+            float med = 0.0f;
+            if (nc > 0) {
+                const int r = (nc - 1) / 2;
+                int q = r + (int)below;
+                if (inb > 0) {
+                    for (int iter = 0; iter <= hmax + 1; ++iter) {
+                        int extra = 0;
+                        int ph = -1;
+                        for (int m = 1; m <= mv; ++m) {
+                            const int cm = (int)centre(m);
+                            const int lo = (cm - ca.dk) > ph + 1 ? (cm - ca.dk) : ph + 1;
+                            const int hi = cm + ca.dk;
+                            for (int k = lo; k <= hi; ++k) {
+                                const uint16_t rk = sRk[k];
+                                if (rk < kAbove && ca.b_lo + (int)rk <= q) ++extra;
+                            }
+                            ph = hi;
+                        }
+                        const int qn = r + (int)below + extra;
+                        if (qn == q) break;
+                        q = qn;
+                    }
+                }
+                // q lies in [b_lo, b_hi] by construction; the clamp only guards memory
+                q = q < ca.b_lo ? ca.b_lo : (q > ca.b_hi ? ca.b_hi : q);
+                med = sBand[q - ca.b_lo];
+            }
+            const float den = med > fden_floor ? med : fden_floor;
+            snr = den > 0.0f ? N / den : 0.0f;
+            if (best_i < 0 || snr > best) { best = snr; best_i = i; }
+        }
+        if (snr_all) snr_all[(int64_t)u * K + i] = snr;
+    }
+    // block argmax: highest score, lowest bin on ties; -1 = none admissible
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) {
+        const float ob = __shfl_xor(best, d, 64);
+        const int oi = __shfl_xor(best_i, d, 64);
+        const bool take = oi >= 0 && (best_i < 0 || ob > best || (ob == best && oi < best_i));
+        if (take) { best = ob; best_i = oi; }
+    }
+    const int w = tid / kWave;
+    if (__lane_id() == 0) { s_best[w] = best; s_bi[w] = best_i; }
+    __syncthreads();
+    if (tid == 0) {
+        float b = 0.0f;
+        int bi = -1;
+        for (int q = 0; q < kCombThreads / kWave; ++q) {
+            const int oi = s_bi[q];
+            if (oi >= 0 && (bi < 0 || s_best[q] > b || (s_best[q] == b && oi < bi))) {
+                b = s_best[q];
+                bi = oi;
+            }
+        }
+        snr_out[u] = bi < 0 ? 0.0f : b;
+        bin_out[u] = bi;
+    }
+}
+
+static size_t comb_lds_bytes(const CombArgs& ca) {
+    const int hist_words = (2 * kHistBins > ca.kpad + 4) ? 2 * kHistBins : ca.kpad + 4;
+    return (size_t)ca.kpad * 4 + (size_t)ca.kpad * 2 * 2 + (size_t)hist_words * 4 +
+           (size_t)(ca.b_hi - ca.b_lo + 1) * 4 + 16;
+}
+
+}  // namespace ddhf
+
+using namespace ddhf;
+
+extern "C" int ddhf_comb_score(const float* power, int32_t n_active, const ddhf_grid_t* grid,
+                               const ddhf_params_t* prm, float* sf, float* snr_best,
+                               int32_t* bin_best, float* snr_all, void* stream) {
+    if (!grid || !prm || n_active < 0) return DDHF_EINVAL;
+    if (grid->K <= 0 || grid->K > 8192 || grid->df <= 0 || grid->f0 < 0) return DDHF_EINVAL;
+    if (prm->M < 1 || prm->M > 32 || prm->dk < 0 || prm->dk > 16 || prm->h_min < 1 ||
+        !(prm->eps_rel >= 0.0f))
+        return DDHF_EINVAL;
+    if (n_active == 0) return DDHF_OK;
+    if (!power || !sf || !snr_best || !bin_best) return DDHF_EINVAL;
+    CombArgs ca;
+    ca.K = grid->K;
+    ca.M = prm->M;
+    ca.dk = prm->dk;
+    ca.h_min = prm->h_min;
+    ca.f0 = grid->f0;
+    ca.df = grid->df;
+    ca.g = (grid->f0 % grid->df == 0) ? grid->f0 / grid->df : -1;
+    ca.eps = prm->eps_rel;
+    const int hmax = prm->M * (2 * prm->dk + 1);
+    int b_lo = (ca.K - hmax - 1) / 2;
+    if (ca.K - hmax - 1 < 0) b_lo = 0;
+    int b_hi = (ca.K - 1) / 2 + hmax;
+    if (b_hi > ca.K - 1) b_hi = ca.K - 1;
+    ca.b_lo = b_lo;
+    ca.b_hi = b_hi;
+    ca.kpad = (ca.K + 3) / 4 * 4;
+    const size_t lds = comb_lds_bytes(ca);
+    if (lds > 64 * 1024) return DDHF_EINVAL;
+    hipStream_t s = as_stream(stream);
+    static bool attr_set = false;
+    if (!attr_set) {
+        (void)hipFuncSetAttribute((const void*)k_comb, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            64 * 1024);
+        attr_set = true;
+    }
+    hipLaunchKernelGGL(k_comb, dim3((unsigned)n_active), dim3(kCombThreads), lds, s, power,
+                       n_active, ca, sf, snr_best, bin_best, snr_all);
+    DDHF_LAUNCH_CHECK();
+    return DDHF_OK;
+}

@@ -1,0 +1,354 @@
+"""GPU parity of each C-ABI call against the FP64 oracle on seeded inputs.
+
+Bars: CSR and active lists bit-exact; power within
+|P32 - P64| <= 1e-4 max(P64, sum a^2); comb on identical FP32 spectra within
+FP32 rounding, masks identical except pixels within 1e-3 of a threshold;
+detection on identical scores bit-exact."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2603_08386_amd import ddhf as D
+from paper_2603_08386_amd import synth
+from paper_2603_08386_amd.synth import Grid, Params
+
+from gpu_common import DEV, banner, oracle_window, power_err, stratified_sample
+
+pytestmark = pytest.mark.gpu
+
+TOL_P = 1e-4
+
+
+def to_np(t, n=None):
+    a = t.detach().cpu().numpy()
+    return a if n is None else a[:n]
+
+
+# ---------------------------------------------------------------------------
+# 1. index
+# ---------------------------------------------------------------------------
+
+def index_cases():
+    return {
+        "tiny": lambda: synth.tiny_window(1),
+        "random_unsorted": lambda: synth.random_window(5, 37, 23, 10_000, 20_000, Grid(1000, 1000, 64), time_sorted=False),
+        "random_spill": lambda: synth.random_window(6, 37, 23, 10_000, 20_000, Grid(1000, 1000, 64), max_t_over=3000, time_sorted=False),
+        "pol01": lambda: synth.random_window(7, 16, 16, 5_000, 3_000, Grid(1000, 1000, 64), polarity01=True),
+        "ragged_tiles": lambda: synth.random_window(8, 300, 200, 50_000, 12_289, Grid(1000, 1000, 64), time_sorted=False),
+        "empty": lambda: synth.random_window(9, 8, 8, 1_000, 0, Grid(1000, 1000, 64)),
+    }
+
+
+@pytest.mark.parametrize("case", list(index_cases().keys()))
+@pytest.mark.parametrize("sorted_flag", [False, True])
+def test_index_bit_exact(case, sorted_flag):
+    win = index_cases()[case]()
+    time_sorted = sorted_flag and bool(np.all(np.diff(win.t) >= 0))
+    banner(f"index {case} n={win.n} time_sorted={time_sorted}")
+    w = None
+    if case == "random_unsorted":
+        w = np.random.default_rng(0).uniform(0.5, 2.0, size=win.n).astype(np.float32)
+    g = D.Window(win.x, win.y, win.p, win.t, win.W, win.H, win.t0, win.T_w, win.grid, win.params,
+                 w=w, device=DEV, time_sorted=time_sorted)
+    g.index()
+    torch.cuda.synchronize()
+    r = oracle.build_pixel_index(win.x, win.y, win.p, win.t, win.W, win.H, win.t0, win.T_w, w=w)
+    m = r["n_kept"]
+    assert np.array_equal(to_np(g.row_ptr), r["row_ptr"])
+    assert np.array_equal(to_np(g.perm, m), r["perm"])
+    assert np.array_equal(to_np(g.t_rel, m).view(np.uint32), r["t_rel"])
+    assert np.array_equal(to_np(g.a, m).astype(np.float64), r["a"])
+    assert np.array_equal(to_np(g.counters), r["counters"])
+    act = oracle.active_pixels(r["row_ptr"], win.params.n_min)
+    na = int(g.n_active_dev.item())
+    assert na == act.shape[0]
+    assert np.array_equal(to_np(g.active, na), act)
+
+
+def test_active_cost_order():
+    win = synth.random_window(11, 120, 90, 50_000, 80_000, Grid(1000, 1000, 64))
+    banner("active cost order")
+    g = D.Window(win.x, win.y, win.p, win.t, win.W, win.H, win.t0, win.T_w, win.grid,
+                 Params(n_min=3), device=DEV, order_by_cost=True)
+    g.index()
+    na = int(g.n_active_dev.item())
+    got = to_np(g.active, na)
+    rp = to_np(g.row_ptr)
+    act = oracle.active_pixels(rp, 3)
+    assert sorted(got.tolist()) == act.tolist()
+    cls = np.floor(np.log2(rp[got + 1] - rp[got])).astype(int)
+    assert np.all(np.diff(cls) <= 0)
+    for c in np.unique(cls):  # ascending pixel inside a class
+        assert np.all(np.diff(got[cls == c]) > 0)
+
+
+# ---------------------------------------------------------------------------
+# 2. NDFT power
+# ---------------------------------------------------------------------------
+
+def gpu_power(win, launch=None, params=None):
+    g = D.Window(win.x, win.y, win.p, win.t, win.W, win.H, win.t0, win.T_w, win.grid,
+                 params or win.params, device=DEV, launch=launch)
+    g.index()
+    g.fetch_n_active()
+    g.alloc_spectra()
+    g.spectra()
+    torch.cuda.synchronize()
+    K = win.grid.K
+    return g, to_np(g.power, g.n_active * K).reshape(g.n_active, K)
+
+
+@pytest.mark.parametrize("bpl", [8, 16, 32, 64])
+def test_ndft_tiny_full(bpl):
+    win = synth.tiny_window(1)
+    banner(f"ndft tiny bpl={bpl}")
+    g, P = gpu_power(win, D.make_launch(D.DDHF_KERNEL_VALU, bpl))
+    r = oracle_window(win)
+    assert np.array_equal(to_np(g.active, g.n_active), r["active"])
+    P64 = oracle.ndft_power(r["row_ptr"], r["t_rel"], r["a"], r["active"], win.grid)
+    err = power_err(P, P64, r["row_ptr"], r["active"], r["a"])
+    banner(f"  max err {err:.3e}")
+    assert err <= TOL_P
+
+
+def test_ndft_mode_grid_and_ragged_bins():
+    """Mode grid (integer modes over the window) with K not a multiple of
+    any tile, T_w = 33,333 us (30 FPS windows)."""
+    grid = Grid(f0=0, df=1, K=1000, mode=1, T_w_us=33_333)
+    win = synth.random_window(21, 40, 30, 33_333, 30_000, grid, params=Params(n_min=2))
+    banner("ndft mode grid")
+    g, P = gpu_power(win)
+    r = oracle_window(win)
+    P64 = oracle.ndft_power(r["row_ptr"], r["t_rel"], r["a"], r["active"], grid)
+    assert power_err(P, P64, r["row_ptr"], r["active"], r["a"]) <= TOL_P
+
+
+def test_ndft_closed_forms_on_gpu():
+    """Coincident events give a flat (sum a)^2 spectrum; a strictly periodic
+    train gives C^2 at its harmonics."""
+    W, H, T_w = 4, 1, 50_000
+    t_coinc = np.full(12, 20_000)
+    T = 4000
+    t_per = 137 + T * np.arange(10)
+    x = np.concatenate([np.zeros(12), np.ones(10)]).astype(np.uint16)
+    t = np.concatenate([t_coinc, t_per]) + synth.T0_US
+    p = np.ones(22, np.int8)
+    o = np.argsort(t, kind="stable")
+    grid = Grid(f0=1000, df=1000, K=2000)
+    win = synth.Window(W, H, synth.T0_US, T_w, x[o], np.zeros(22, np.uint16), p[o], t[o], grid,
+                       Params(n_min=1), np.zeros((1, 4), bool), {})
+    banner("ndft closed forms")
+    g, P = gpu_power(win)
+    assert np.allclose(P[0], 144.0, rtol=1e-5)
+    for n in range(1, 8):
+        assert P[1][250 * n - 1] == pytest.approx(100.0, rel=1e-4)
+
+
+def test_ndft_medium_sampled():
+    win = synth.medium_window(2)
+    banner(f"ndft medium n={win.n}")
+    g, P = gpu_power(win)
+    r = oracle_window(win)
+    assert np.array_equal(to_np(g.active, g.n_active), r["active"])
+    rp = r["row_ptr"]
+    counts = rp[r["active"] + 1] - rp[r["active"]]
+    rows = stratified_sample(counts, 60, np.random.default_rng(0))
+    P64 = oracle.ndft_power(rp, r["t_rel"], r["a"], r["active"][rows], win.grid)
+    err = power_err(P[rows], P64, rp, r["active"][rows], r["a"])
+    banner(f"  sampled rows {rows.size} max err {err:.3e}")
+    assert err <= TOL_P
+
+
+def test_ndft_deterministic():
+    win = synth.tiny_window(3)
+    _, P1 = gpu_power(win)
+    _, P2 = gpu_power(win)
+    assert np.array_equal(P1, P2)
+
+
+def test_ndft_empty_and_degenerate():
+    grid = Grid(f0=1000, df=1000, K=300)
+    win = synth.random_window(30, 8, 8, 1000, 0, grid, params=Params(n_min=1))
+    g, P = gpu_power(win)
+    assert g.n_active == 0
+    # a single event in a single pixel: |a|^2 everywhere
+    win = synth.random_window(31, 1, 1, 1000, 1, grid, params=Params(n_min=1))
+    g, P = gpu_power(win)
+    assert np.allclose(P, 1.0, rtol=1e-6)
+
+
+# ---------------------------------------------------------------------------
+# 3. comb score on identical FP32 spectra
+# ---------------------------------------------------------------------------
+
+def run_comb(P32, grid, prm, want_all=False):
+    n, K = P32.shape
+    dev = torch.from_numpy(np.ascontiguousarray(P32)).to(DEV)
+    sf = torch.empty(n, dtype=torch.float32, device=DEV)
+    snr = torch.empty(n, dtype=torch.float32, device=DEV)
+    b = torch.empty(n, dtype=torch.int32, device=DEV)
+    allv = torch.empty(n * K, dtype=torch.float32, device=DEV) if want_all else None
+    D.ddhf_comb_score(dev, n, D.make_grid(grid), D.make_params(prm), sf, snr, b, allv)
+    torch.cuda.synchronize()
+    out = (to_np(sf), to_np(snr), to_np(b))
+    if want_all:
+        out = out + (to_np(allv).reshape(n, K),)
+    return out
+
+
+def comb_compare(P32, grid, prm, check_all=True):
+    sf, snr, b, allv = run_comb(P32, grid, prm, want_all=True)
+    for u in range(P32.shape[0]):
+        P = P32[u].astype(np.float64)
+        sf64 = oracle.spectral_flatness(P, prm.eps_rel)
+        s64, b64, all64 = oracle.comb_score(P, grid, prm, want_all=True)
+        assert sf[u] == pytest.approx(sf64, rel=2e-5, abs=1e-7), u
+        assert snr[u] == pytest.approx(s64, rel=2e-5, abs=1e-7), u
+        if check_all:
+            assert np.allclose(allv[u], all64, rtol=2e-5, atol=1e-7), u
+        top = np.sort(all64)[::-1]
+        if top.size < 2 or top[0] > (1 + 1e-3) * top[1]:
+            assert b[u] == b64, u
+
+
+def test_comb_on_oracle_spectra_tiny():
+    win = synth.tiny_window(1)
+    r = oracle_window(win)
+    P64 = oracle.ndft_power(r["row_ptr"], r["t_rel"], r["a"], r["active"], win.grid)
+    banner(f"comb tiny rows={P64.shape[0]}")
+    comb_compare(P64.astype(np.float32), win.grid, win.params)
+
+
+def test_comb_random_spectra_many_shapes():
+    rng = np.random.default_rng(5)
+    for K, M, dk, hmin, f0, df in [(1024, 5, 3, 3, 1000, 1000), (3981, 4, 3, 4, 10_000, 500),
+                                   (3991, 4, 3, 4, 10_000, 1000), (777, 6, 2, 2, 750, 500),
+                                   (129, 3, 0, 2, 0, 1), (300, 16, 4, 8, 10_000, 500)]:
+        grid = Grid(f0=f0, df=df, K=K)
+        prm = Params(M=M, dk=dk, h_min=hmin)
+        P = rng.exponential(size=(6, K)).astype(np.float32)
+        P[1] *= 1e-20
+        P[2, ::7] = 0.0                       # zeros
+        P[3] = np.round(P[3] * 4) / 4         # many ties
+        P[4] = 1.0                            # flat: all ties
+        P[5, 5::37] += 50.0                   # comb-like spikes
+        banner(f"comb random K={K} M={M} dk={dk}")
+        comb_compare(P, grid, prm)
+
+
+def test_comb_zero_spectrum():
+    grid = Grid(f0=10_000, df=500, K=400)
+    sf, snr, b = run_comb(np.zeros((2, 400), np.float32), grid, Params())
+    assert np.all(sf == 1.0) and np.all(snr == 0.0)
+    best64, b64 = oracle.comb_score(np.zeros(400), grid, Params())
+    assert np.all(b == b64)
+
+
+# ---------------------------------------------------------------------------
+# 4. detect on identical inputs
+# ---------------------------------------------------------------------------
+
+def run_detect(active, row_ptr, sf, snr, b, W, H, grid, prm, max_boxes=512):
+    t = lambda a, dt: torch.from_numpy(np.ascontiguousarray(a, dt)).to(DEV)
+    na = int(active.shape[0])
+    mask = torch.empty(W * H, dtype=torch.uint8, device=DEV)
+    labels = torch.empty(W * H, dtype=torch.int32, device=DEV)
+    boxes = torch.empty(max_boxes * 32, dtype=torch.uint8, device=DEV)
+    nb = torch.zeros(2, dtype=torch.int32, device=DEV)
+    ws = D.workspace(D.ddhf_detect_workspace_size(W, H), DEV)
+    D.ddhf_detect(t(active if na else np.zeros(1), np.int32), t(row_ptr, np.int32),
+                  t(sf if na else np.zeros(1), np.float32), t(snr if na else np.zeros(1), np.float32),
+                  t(b if na else np.zeros(1), np.int32), na, W, H, D.make_grid(grid),
+                  D.make_params(prm), mask, labels, boxes, max_boxes, nb, ws)
+    torch.cuda.synchronize()
+    n = int(nb[0].item())
+    return to_np(mask), to_np(labels), D.boxes_to_list(boxes, min(n, max_boxes)), n, int(nb[1].item())
+
+
+def detect_compare(active, row_ptr, sf, snr, b, W, H, grid, prm):
+    sf32, snr32 = sf.astype(np.float32), snr.astype(np.float32)
+    m, lab, boxes, n, dropped = run_detect(active, row_ptr, sf32, snr32, b, W, H, grid, prm)
+    tau = Params(**{**prm.__dict__})
+    tau.tau_sf = float(np.float32(prm.tau_sf))
+    tau.tau_comb = float(np.float32(prm.tau_comb))
+    tau.alpha = float(np.float32(prm.alpha))
+    m64, lab64, boxes64, n64 = oracle.detect(active, row_ptr, sf32.astype(np.float64),
+                                             snr32.astype(np.float64), b, W, H, grid, tau)
+    assert np.array_equal(m, m64)
+    assert np.array_equal(lab, lab64)
+    assert n == n64 and dropped == 0
+    assert len(boxes) == len(boxes64)
+    for g1, o1 in zip(boxes, boxes64):
+        for k in ["x0", "y0", "x1", "y1", "n_px", "rep_pixel"]:
+            assert g1[k] == o1[k], (k, g1, o1)
+        assert g1["rep_snr"] == o1["rep_snr"]
+        assert g1["f_dom_hz"] == pytest.approx(o1["f_dom_hz"], rel=1e-7)
+    return n
+
+
+@pytest.mark.parametrize("density", [0.02, 0.2, 0.5])
+@pytest.mark.parametrize("alpha", [0.0, 1.5, 19.05])
+def test_detect_random_masks(density, alpha):
+    rng = np.random.default_rng(int(density * 1000 + alpha * 10))
+    W, H = 96, 64
+    n = W * H
+    counts = rng.integers(0, 12, size=n)
+    row_ptr = np.concatenate([[0], np.cumsum(counts)]).astype(np.int32)
+    active = np.flatnonzero(counts >= 6).astype(np.int32)
+    on = rng.random(active.size) < density * 1.6
+    sf = np.where(on, rng.uniform(0.1, 0.85, active.size), rng.uniform(0.3, 1.0, active.size))
+    snr = np.where(on, rng.uniform(1.5, 9.0, active.size), rng.uniform(0.0, 3.0, active.size))
+    b = rng.integers(0, 3981, size=active.size).astype(np.int32)
+    grid = Grid(f0=10_000, df=500, K=3981)
+    prm = Params(a_min=4, alpha=alpha)
+    banner(f"detect density={density} alpha={alpha}")
+    detect_compare(active, row_ptr, sf, snr, b, W, H, grid, prm)
+
+
+def test_detect_on_oracle_scores_tiny():
+    win = synth.tiny_window(1)
+    r = oracle_window(win)
+    P64 = oracle.ndft_power(r["row_ptr"], r["t_rel"], r["a"], r["active"], win.grid)
+    sf, snr, b = oracle.score_rows(P64, win.grid, win.params)
+    n = detect_compare(r["active"], r["row_ptr"], sf, snr, b, win.W, win.H, win.grid, win.params)
+    assert n >= 1
+
+
+def test_detect_empty():
+    grid = Grid(f0=10_000, df=500, K=3981)
+    m, lab, boxes, n, _ = run_detect(np.zeros(0, np.int32), np.zeros(17, np.int32), np.zeros(0),
+                                     np.zeros(0), np.zeros(0, np.int32), 4, 4, grid, Params())
+    assert n == 0 and not m.any() and np.all(lab == -1)
+
+
+# ---------------------------------------------------------------------------
+# 5. end to end: events -> boxes
+# ---------------------------------------------------------------------------
+
+def near_threshold(sf, snr, prm):
+    return (np.abs(sf / prm.tau_sf - 1) <= 1e-3) | (np.abs(snr / prm.tau_comb - 1) <= 1e-3)
+
+
+def test_end_to_end_tiny():
+    win = synth.tiny_window(1)
+    banner("end to end tiny")
+    g = D.window_from_synth(win, device=DEV)
+    boxes, n, dropped = g.run()
+    r = oracle_window(win)
+    P64 = oracle.ndft_power(r["row_ptr"], r["t_rel"], r["a"], r["active"], win.grid)
+    sf, snr, b = oracle.score_rows(P64, win.grid, win.params)
+    m64, lab64, boxes64, n64 = oracle.detect(r["active"], r["row_ptr"], sf, snr, b, win.W, win.H,
+                                             win.grid, win.params)
+    mask = to_np(g.mask)
+    amb = np.zeros(win.W * win.H, bool)
+    amb[r["active"]] = near_threshold(sf, snr, win.params)
+    assert np.array_equal(mask[~amb], m64[~amb])
+    # scores within tolerance of the FP64 path
+    assert np.allclose(to_np(g.sf, g.n_active), sf, rtol=1e-3, atol=1e-6)
+    if not amb.any():
+        assert n == n64
+        assert [(q["x0"], q["y0"], q["x1"], q["y1"], q["n_px"]) for q in boxes] == \
+               [(q["x0"], q["y0"], q["x1"], q["y1"], q["n_px"]) for q in boxes64]
+    # the single synthetic drone is found
+    assert n >= 1
