@@ -176,11 +176,15 @@ int ddhf_ndft_workspace_size(int32_t n_active, int64_t n_events, const ddhf_grid
  * F_u(f) = sum over the events of pixel active[u] of a_e exp(i 2 pi r / Q),
  * r = (f t_rel) mod Q (exact integer residue), FP32 sin/cos and accumulation.
  * Inputs are the outputs of calls 1 and 2 (n_active is the host copy of the
- * count).  launch may be NULL (plain).  Error against FP64:
+ * count; n_events is the number of CSR events or any upper bound, e.g. the
+ * window's input count, and must match the workspace request).  launch may be
+ * NULL (plain).  Split pixels are summed in a fixed chunk order: results are
+ * deterministic for a given launch.  Error against FP64:
  * |P - P64| <= 1e-4 max(P64, sum_e a_e^2) per pixel and bin. */
 int ddhf_ndft_power(const int32_t* row_ptr, const uint32_t* t_rel, const float* a,
-                    const int32_t* active, int32_t n_active, const ddhf_grid_t* grid, float* power,
-                    const ddhf_launch_t* launch, void* ws, size_t ws_bytes, void* stream);
+                    const int32_t* active, int32_t n_active, int64_t n_events,
+                    const ddhf_grid_t* grid, float* power, const ddhf_launch_t* launch, void* ws,
+                    size_t ws_bytes, void* stream);
 
 /* ---- 4. spectral flatness + harmonic comb (Eq. 7-11) --------------------- */
 
@@ -219,6 +223,97 @@ int ddhf_detect(const int32_t* active, const int32_t* row_ptr, const float* sf,
                 int32_t H, const ddhf_grid_t* grid, const ddhf_params_t* prm, uint8_t* mask,
                 int32_t* labels, ddhf_box_t* boxes, int32_t max_boxes, int32_t* n_boxes, void* ws,
                 size_t ws_bytes, void* stream);
+
+/* ---- 6. soft comb score and gradients (a differentiable relaxation of the
+ *         comb of Eq. 8-11 for tuning weights and thresholds) ------------ */
+
+/* For active pixel u with fundamental f0_mhz[u] (integer mHz, typically the
+ * hard path's dominant frequency; 0 disables the pixel) and its n_u events in
+ * CSR order (t_rel from call 1):
+ *   F_uh  = sum_e sgn_e e_e exp(i theta_eh),  h = 1..nh (nh <= 16)
+ *   theta = 2 pi [((h f0 t_e) mod 1e9) / 1e9 + h f0 dt_e / 1e9]  (exact residue)
+ *   P^_uh = |F_uh|^2 / n_u for h f0 <= f_max_mhz, else 0
+ *   s_u   = 1 / (1 + exp(-beta (sum_h w_h P^_uh - tau)))
+ * sgn, e, dt: per-event arrays in CSR order (sign +-1, weight, time offset in
+ * us); w [nh] and tau [1] are device arrays.  dtype 0 = every floating array
+ * is f32, 1 = f64.  Outputs: s [n_active], phat [n_active * nh],
+ * F [n_active * nh * 2] (re, im), kept for the backward call. */
+int ddhf_soft_comb_forward(const int32_t* row_ptr, const uint32_t* t_rel, const void* sgn,
+                           const void* e, const void* dt, const int32_t* active, int32_t n_active,
+                           const int64_t* f0_mhz, int32_t nh, int64_t f_max_mhz, const void* w,
+                           const void* tau, double beta, int32_t dtype, void* s, void* phat,
+                           void* F, void* stream);
+
+int ddhf_soft_comb_backward_workspace_size(int32_t n_active, int32_t nh, int32_t dtype,
+                                           size_t* bytes);
+
+/* Given g_s = dL/ds [n_active], writes dL/dw [nh], dL/dtau [1], and per-event
+ * dL/de [n] and dL/ddt [n] (per us) in CSR order.  Reductions over pixels are
+ * done in a fixed order (deterministic). */
+int ddhf_soft_comb_backward(const int32_t* row_ptr, const uint32_t* t_rel, const void* sgn,
+                            const void* e, const void* dt, const int32_t* active, int32_t n_active,
+                            const int64_t* f0_mhz, int32_t nh, int64_t f_max_mhz, const void* w,
+                            double beta, int32_t dtype, const void* s, const void* phat,
+                            const void* F, const void* g_s, void* g_w, void* g_tau, void* g_e,
+                            void* g_dt, void* ws, size_t ws_bytes, void* stream);
+
+/* ---- 7. streaming: sliding window over a continuous event stream --------- */
+
+/* The window [t_now - T_w, t_now) slides with each step.  Per-pixel rings on
+ * the device hold each pixel's events of the window; only pixels that gain or
+ * lose events are recomputed (their NDFT power, Eq. 6, and comb score,
+ * Eq. 7-11); the frame's mask, components and boxes are then rebuilt
+ * (Sec. 3.5).  All launches of a step can be captured once in a hipGraph. */
+typedef struct {
+    int32_t W, H;
+    int64_t T_w_us;          /* window length (< 2^31 us) */
+    int64_t t_origin_us;     /* stream epoch: earlier events are rejected; stream < 2^32 us */
+    int32_t ring_cap;        /* events kept per pixel (power of two, 2..4096); extra = oldest lost */
+    int32_t max_step_events; /* events staged between two steps */
+    int32_t max_touched;     /* pixels that may change in one step */
+    int32_t max_boxes;
+    ddhf_grid_t grid;        /* Hz grid */
+    ddhf_params_t params;
+    ddhf_launch_t launch;    /* NDFT kernel and tile for the recomputed pixels (plain form) */
+} ddhf_stream_cfg_t;
+
+typedef struct ddhf_stream ddhf_stream_t;
+
+typedef struct {
+    int64_t steps;
+    int64_t events_accepted;
+    int64_t events_rejected;  /* outside the sensor or window, bad polarity */
+    int64_t ring_overflow;    /* events lost because a pixel's ring was full */
+    int64_t touched_overflow; /* pixel updates lost because max_touched was exceeded */
+    int32_t n_active;         /* after the last step */
+    int32_t n_touched;
+    int32_t n_recomputed;
+    int32_t reserved;
+} ddhf_stream_stats_t;
+
+/* Allocates the device state (rings, log, scores, scratch) and pinned staging
+ * memory; this is the only allocating call of the stream API. */
+int ddhf_stream_create(const ddhf_stream_cfg_t* cfg, ddhf_stream_t** out);
+int ddhf_stream_destroy(ddhf_stream_t* st);
+
+/* Stages n host events (x, y, p, t in host memory) for the next step.  Events
+ * must be time ordered within and across pushes.  DDHF_ENOSPACE if more than
+ * max_step_events are staged before a step. */
+int ddhf_stream_push(ddhf_stream_t* st, const uint16_t* x, const uint16_t* y, const int8_t* p,
+                     const int64_t* t_us, int32_t n);
+
+/* Runs one step with window end t_now_us (>= the last staged time) on the
+ * stream's own HIP stream (graph-launched if use_graph != 0), waits for it, and
+ * copies up to max_boxes boxes to boxes_host; *n_boxes_host = number of boxes.
+ * DDHF_ENOSPACE if the window would hold more events than the device log. */
+int ddhf_stream_step(ddhf_stream_t* st, int64_t t_now_us, int32_t use_graph,
+                     ddhf_box_t* boxes_host, int32_t max_boxes, int32_t* n_boxes_host);
+
+int ddhf_stream_stats(ddhf_stream_t* st, ddhf_stream_stats_t* out);
+
+/* Copies the per-pixel state [W*H] to device arrays (each nullable): flatness,
+ * comb SNR, dominant bin (-1 if inactive), and the pixel's event count. */
+int ddhf_stream_scores(ddhf_stream_t* st, float* sf, float* snr, int32_t* bin, int32_t* count);
 
 #ifdef __cplusplus
 }

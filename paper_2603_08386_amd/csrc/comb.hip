@@ -77,7 +77,8 @@ __global__ __launch_bounds__(kCombThreads) void k_comb(const float* __restrict__
                                                        float* __restrict__ sf_out,
                                                        float* __restrict__ snr_out,
                                                        int32_t* __restrict__ bin_out,
-                                                       float* __restrict__ snr_all) {
+                                                       float* __restrict__ snr_all,
+                                                       const int32_t* __restrict__ n_dev) {
     extern __shared__ __align__(16) char smem[];
     const int K = ca.K;
     float* sP = (float*)smem;                                  // [kpad]
@@ -95,7 +96,7 @@ __global__ __launch_bounds__(kCombThreads) void k_comb(const float* __restrict__
 
     const int tid = threadIdx.x;
     const int32_t u = blockIdx.x;
-    if (u >= n_active) return;
+    if (u >= n_active || (n_dev && u >= *n_dev)) return;
     const float* row = power + (int64_t)u * K;
     if (tid == 0) {
         s_b1lo = s_b1hi = s_b2lo = s_b2hi = 0;
@@ -327,6 +328,331 @@ __global__ __launch_bounds__(kCombThreads) void k_comb(const float* __restrict__
     }
 }
 
+// ---------------------------------------------------------------------------
+// Fast path (K <= 4095, band <= 254): the row stays in registers across
+// phases, the band is found by a three-level 8-bit radix select (exponent,
+// then 8 + 8 mantissa bits; the 24-bit prefix orders the values), and one u32
+// per bin packs the exclusive prefix counts of below-band bins (bits 0-11) and
+// in-band bins (bits 12-19) with the bin's own band index (bits 24-31, 0xFF if
+// outside the band).
+// ---------------------------------------------------------------------------
+constexpr int kFastItems = 16;    // bins per thread: K <= 4096
+constexpr int kListCap = 1024;
+
+struct Loc {
+    int d;
+    uint32_t before;
+};
+
+// Locate, in a 256-bucket histogram (one bucket per thread) offset by `base`,
+// the bucket holding rank tgt; returns it in *out (only one thread writes).
+__device__ __forceinline__ void locate256(const uint32_t* h, uint32_t base, int32_t tgt, Loc* out,
+                                          uint32_t* scr) {
+    const int tid = threadIdx.x;
+    const uint32_t c = h[tid];
+    const uint32_t incl = wave_incl_scan(c);
+    const int w = tid / kWave;
+    if (__lane_id() == kWave - 1) scr[w] = incl;
+    __syncthreads();
+    uint32_t before = base + incl - c;
+    for (int k = 0; k < w; ++k) before += scr[k];
+    if ((int64_t)before <= tgt && tgt < (int64_t)(before + c)) {
+        out->d = tid;
+        out->before = before;
+    }
+    __syncthreads();
+}
+
+template <int DK>
+__global__ __launch_bounds__(kCombThreads) void k_comb_fast(const float* __restrict__ power,
+                                                            int32_t n_active, CombArgs ca,
+                                                            int32_t i_max,
+                                                            float* __restrict__ sf_out,
+                                                            float* __restrict__ snr_out,
+                                                            int32_t* __restrict__ bin_out,
+                                                            float* __restrict__ snr_all,
+                                                            const int32_t* __restrict__ n_dev) {
+    extern __shared__ __align__(16) char smem[];
+    float* sP = (float*)smem;                       // [kpad]
+    uint32_t* sCnt = (uint32_t*)(sP + ca.kpad);     // [kpad + 4]
+    __shared__ uint32_t hA[256], hB[256];
+    __shared__ float sBand[256];
+    __shared__ uint16_t sList[kListCap];
+    __shared__ double red[kCombThreads / kWave];
+    __shared__ uint32_t scr[kCombThreads / kWave];
+    __shared__ Loc l1lo, l1hi, l2lo, l2hi, l3lo, l3hi;
+    __shared__ uint32_t s_nlist;
+    __shared__ float s_best[kCombThreads / kWave];
+    __shared__ int s_bi[kCombThreads / kWave];
+
+    const int K = ca.K;
+    const int dk = DK >= 0 ? DK : ca.dk;
+    const int tid = threadIdx.x;
+    const int32_t u = blockIdx.x;
+    if (u >= n_active || (n_dev && u >= *n_dev)) return;
+    const float* row = power + (int64_t)u * K;
+
+    hA[tid] = 0;
+    hB[tid] = 0;
+    if (tid == 0) {
+        l1lo = l1hi = l2lo = l2hi = l3lo = l3hi = Loc{0, 0};
+        s_nlist = 0;
+    }
+    // ---- P1: load (all loads in flight), sum, exponent histogram ----------
+    float v[kFastItems];
+#pragma unroll
+    for (int i = 0; i < kFastItems; ++i) {
+        const int k = tid + i * kCombThreads;
+        v[i] = k < K ? row[k] : 0.0f;
+    }
+    __syncthreads();
+    double sum = 0.0;
+#pragma unroll
+    for (int i = 0; i < kFastItems; ++i) {
+        const int k = tid + i * kCombThreads;
+        if (k < K) {
+            sP[k] = v[i];
+            sum += (double)v[i];
+            atomicAdd(&hA[(__float_as_uint(v[i]) >> 23) & 0xFF], 1u);
+        }
+    }
+    sum = block_sum_d(sum, red);
+    const double mean = sum / (double)K;
+    const float floor_v = (float)(ca.eps * mean);
+    locate256(hA, 0, ca.b_lo, &l1lo, scr);
+    locate256(hA, 0, ca.b_hi, &l1hi, scr);
+    const int d1lo = l1lo.d, d1hi = l1hi.d;
+    hA[tid] = 0;
+    hB[tid] = 0;
+    __syncthreads();
+    // ---- P2: log-sum (Eq. 7) and second digit ----------------------------
+    double sl = 0.0;
+#pragma unroll
+    for (int i = 0; i < kFastItems; ++i) {
+        const int k = tid + i * kCombThreads;
+        if (k < K) {
+            sl += (double)__log2f(v[i] > floor_v ? v[i] : floor_v);
+            const uint32_t b = __float_as_uint(v[i]);
+            const int d1 = (b >> 23) & 0xFF;
+            if (d1 == d1lo) atomicAdd(&hA[(b >> 15) & 0xFF], 1u);
+            if (d1 == d1hi) atomicAdd(&hB[(b >> 15) & 0xFF], 1u);
+        }
+    }
+    sl = block_sum_d(sl, red);
+    if (tid == 0) sf_out[u] = mean > 0.0 ? (float)exp2(sl / (double)K - log2(mean)) : 1.0f;
+    locate256(hA, l1lo.before, ca.b_lo, &l2lo, scr);
+    locate256(hB, l1hi.before, ca.b_hi, &l2hi, scr);
+    const uint32_t p2lo = ((uint32_t)d1lo << 8) | (uint32_t)l2lo.d;
+    const uint32_t p2hi = ((uint32_t)d1hi << 8) | (uint32_t)l2hi.d;
+    hA[tid] = 0;
+    hB[tid] = 0;
+    __syncthreads();
+    // ---- P3: third digit --------------------------------------------------
+#pragma unroll
+    for (int i = 0; i < kFastItems; ++i) {
+        const int k = tid + i * kCombThreads;
+        if (k < K) {
+            const uint32_t b = __float_as_uint(v[i]);
+            const uint32_t p2 = (b >> 15) & 0xFFFF;
+            if (p2 == p2lo) atomicAdd(&hA[(b >> 7) & 0xFF], 1u);
+            if (p2 == p2hi) atomicAdd(&hB[(b >> 7) & 0xFF], 1u);
+        }
+    }
+    __syncthreads();
+    locate256(hA, l2lo.before, ca.b_lo, &l3lo, scr);
+    locate256(hB, l2hi.before, ca.b_hi, &l3hi, scr);
+    const uint32_t key_lo = (p2lo << 8) | (uint32_t)l3lo.d;
+    const uint32_t key_hi = (p2hi << 8) | (uint32_t)l3hi.d;
+    const uint32_t below_base = l3lo.before;
+    // ---- P4: classify; rank the band candidates -------------------------
+    // temporary codes in sCnt: 0 below, 1 above, 2 candidate, 0x100 + idx in band
+#pragma unroll
+    for (int i = 0; i < kFastItems; ++i) {
+        const int k = tid + i * kCombThreads;
+        if (k < K) {
+            const uint32_t kk = __float_as_uint(v[i]) >> 7;
+            uint32_t code = kk < key_lo ? 0u : (kk > key_hi ? 1u : 2u);
+            if (code == 2u) {
+                const uint32_t pos = atomicAdd(&s_nlist, 1u);
+                if (pos < kListCap) sList[pos] = (uint16_t)k;
+            }
+            sCnt[k] = code;
+        }
+    }
+    __syncthreads();
+    const int nL = (int)s_nlist;
+    if (nL <= kListCap) {
+        for (int a = tid; a < nL; a += kCombThreads) {
+            const int ki = sList[a];
+            const float vi = sP[ki];
+            uint32_t r = 0;
+            for (int b = 0; b < nL; ++b) {
+                const int kj = sList[b];
+                const float vj = sP[kj];
+                r += (vj < vi || (vj == vi && kj < ki)) ? 1u : 0u;
+            }
+            const int full = (int)(below_base + r);
+            if (full < ca.b_lo) sCnt[ki] = 0u;
+            else if (full > ca.b_hi) sCnt[ki] = 1u;
+            else { sCnt[ki] = 0x100u + (uint32_t)(full - ca.b_lo); sBand[full - ca.b_lo] = vi; }
+        }
+    } else {
+        // many exact ties: rank each candidate against every candidate bin
+#pragma unroll 1
+        for (int i = 0; i < kFastItems; ++i) {
+            const int ki = tid + i * kCombThreads;
+            if (ki >= K || (__float_as_uint(v[i]) >> 7) < key_lo || (__float_as_uint(v[i]) >> 7) > key_hi)
+                continue;
+            const float vi = v[i];
+            uint32_t r = 0;
+            for (int kj = 0; kj < K; ++kj) {
+                const float vj = sP[kj];
+                const uint32_t kk = __float_as_uint(vj) >> 7;
+                if (kk >= key_lo && kk <= key_hi && (vj < vi || (vj == vi && kj < ki))) ++r;
+            }
+            const int full = (int)(below_base + r);
+            uint32_t code;
+            if (full < ca.b_lo) code = 0u;
+            else if (full > ca.b_hi) code = 1u;
+            else { code = 0x100u + (uint32_t)(full - ca.b_lo); sBand[full - ca.b_lo] = vi; }
+            sCnt[ki] = code;
+        }
+    }
+    __syncthreads();
+    // ---- P5: packed prefix counts over contiguous segments ----------------
+    {
+        const int seg = (K + kCombThreads - 1) / kCombThreads;  // <= 16
+        const int k0 = tid * seg;
+        uint32_t code[kFastItems];
+        uint32_t s = 0;
+#pragma unroll
+        for (int j = 0; j < kFastItems; ++j) {
+            const int k = k0 + j;
+            code[j] = (j < seg && k < K) ? sCnt[k] : 1u;
+            s += code[j] == 0u ? 1u : (code[j] >= 0x100u ? 0x1000u : 0u);
+        }
+        const uint32_t incl = wave_incl_scan(s);
+        const int w = tid / kWave;
+        if (__lane_id() == kWave - 1) scr[w] = incl;
+        __syncthreads();
+        uint32_t run = incl - s;
+        for (int q = 0; q < w; ++q) run += scr[q];
+#pragma unroll
+        for (int j = 0; j < kFastItems; ++j) {
+            const int k = k0 + j;
+            if (j < seg && k < K) {
+                const uint32_t rk = code[j] >= 0x100u ? (code[j] - 0x100u) : 0xFFu;
+                sCnt[k] = run | (rk << 24);
+                run += code[j] == 0u ? 1u : (code[j] >= 0x100u ? 0x1000u : 0u);
+            }
+        }
+        if (k0 < K && k0 + seg >= K) sCnt[K] = run;
+    }
+    __syncthreads();
+    // ---- P6: candidates (Eq. 8-11) ----------------------------------------
+    const float fden_floor = (float)(ca.eps * mean);
+    const int hmax = ca.M * (2 * dk + 1);
+    float best = 0.0f;
+    int best_i = -1;
+    for (int i = dk + tid; i <= i_max; i += kCombThreads) {
+        auto centre = [&](int m) -> int {
+            if (ca.g >= 0) return (m - 1) * (int)ca.g + m * i;
+            const double num = (double)(m - 1) * (double)ca.f0 + (double)m * (double)i * (double)ca.df;
+            return (int)floor(num / (double)ca.df + 0.5);
+        };
+        int mv = 0;
+        for (int m = 1; m <= ca.M; ++m) {
+            if (centre(m) + dk > K - 1) break;
+            mv = m;
+        }
+        float snr = 0.0f;
+        if (mv >= ca.h_min) {
+            float smax = 0.0f;
+            int hsize = 0;
+            uint32_t below = 0, inb = 0;
+            int prev_hi = -1;
+            for (int m = 1; m <= mv; ++m) {
+                const int cm = centre(m);
+                float mx = sP[cm - dk];
+                if (DK >= 0) {
+#pragma unroll
+                    for (int k = 1; k <= 2 * (DK >= 0 ? DK : 0); ++k) mx = fmaxf(mx, sP[cm - dk + k]);
+                } else {
+                    for (int k = 1; k <= 2 * dk; ++k) mx = fmaxf(mx, sP[cm - dk + k]);
+                }
+                smax += mx;
+                const int lo = (cm - dk) > prev_hi + 1 ? (cm - dk) : prev_hi + 1;
+                const int hi = cm + dk;
+                if (lo <= hi) {
+                    hsize += hi - lo + 1;
+                    const uint32_t d = (sCnt[hi + 1] & 0xFFFFFu) - (sCnt[lo] & 0xFFFFFu);
+                    below += d & 0xFFFu;
+                    inb += d >> 12;
+                }
+                prev_hi = hi;
+            }
+            const float N = smax / (float)mv;
+            const int nc = K - hsize;
+            float med = 0.0f;
+            if (nc > 0) {
+                const int r = (nc - 1) / 2;
+                int q = r + (int)below;
+                if (inb > 0) {
+                    for (int iter = 0; iter <= hmax + 1; ++iter) {
+                        int extra = 0;
+                        int ph = -1;
+                        for (int m = 1; m <= mv; ++m) {
+                            const int cm = centre(m);
+                            const int lo = (cm - dk) > ph + 1 ? (cm - dk) : ph + 1;
+                            for (int k = lo; k <= cm + dk; ++k) {
+                                const uint32_t rk = sCnt[k] >> 24;
+                                if (rk != 0xFFu && ca.b_lo + (int)rk <= q) ++extra;
+                            }
+                            ph = cm + dk;
+                        }
+                        const int qn = r + (int)below + extra;
+                        if (qn == q) break;
+                        q = qn;
+                    }
+                }
+                q = q < ca.b_lo ? ca.b_lo : (q > ca.b_hi ? ca.b_hi : q);
+                med = sBand[q - ca.b_lo];
+            }
+            const float den = med > fden_floor ? med : fden_floor;
+            snr = den > 0.0f ? N / den : 0.0f;
+            if (best_i < 0 || snr > best) { best = snr; best_i = i; }
+        }
+        if (snr_all) snr_all[(int64_t)u * K + i] = snr;
+    }
+    if (snr_all) {
+        for (int i = tid; i < K; i += kCombThreads)
+            if (i < dk || i > i_max) snr_all[(int64_t)u * K + i] = 0.0f;
+    }
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) {
+        const float ob = __shfl_xor(best, d, 64);
+        const int oi = __shfl_xor(best_i, d, 64);
+        const bool take = oi >= 0 && (best_i < 0 || ob > best || (ob == best && oi < best_i));
+        if (take) { best = ob; best_i = oi; }
+    }
+    const int w = tid / kWave;
+    if (__lane_id() == 0) { s_best[w] = best; s_bi[w] = best_i; }
+    __syncthreads();
+    if (tid == 0) {
+        float b = 0.0f;
+        int bi = -1;
+        for (int q = 0; q < kCombThreads / kWave; ++q) {
+            const int oi = s_bi[q];
+            if (oi >= 0 && (bi < 0 || s_best[q] > b || (s_best[q] == b && oi < bi))) {
+                b = s_best[q];
+                bi = oi;
+            }
+        }
+        snr_out[u] = bi < 0 ? 0.0f : b;
+        bin_out[u] = bi;
+    }
+}
+
 static size_t comb_lds_bytes(const CombArgs& ca) {
     const int hist_words = (2 * kHistBins > ca.kpad + 4) ? 2 * kHistBins : ca.kpad + 4;
     return (size_t)ca.kpad * 4 + (size_t)ca.kpad * 2 * 2 + (size_t)hist_words * 4 +
@@ -337,9 +663,10 @@ static size_t comb_lds_bytes(const CombArgs& ca) {
 
 using namespace ddhf;
 
-extern "C" int ddhf_comb_score(const float* power, int32_t n_active, const ddhf_grid_t* grid,
-                               const ddhf_params_t* prm, float* sf, float* snr_best,
-                               int32_t* bin_best, float* snr_all, void* stream) {
+namespace ddhf {
+int comb_run(const float* power, int32_t n_active, const int32_t* n_dev, const ddhf_grid_t* grid,
+             const ddhf_params_t* prm, float* sf, float* snr_best, int32_t* bin_best,
+             float* snr_all, hipStream_t s) {
     if (!grid || !prm || n_active < 0) return DDHF_EINVAL;
     if (grid->K <= 0 || grid->K > 8192 || grid->df <= 0 || grid->f0 < 0) return DDHF_EINVAL;
     if (prm->M < 1 || prm->M > 32 || prm->dk < 0 || prm->dk > 16 || prm->h_min < 1 ||
@@ -364,17 +691,56 @@ extern "C" int ddhf_comb_score(const float* power, int32_t n_active, const ddhf_
     ca.b_lo = b_lo;
     ca.b_hi = b_hi;
     ca.kpad = (ca.K + 3) / 4 * 4;
+    // largest candidate whose first h_min windows stay in band (centres grow with i)
+    auto centre_h = [&](int64_t m, int64_t i) -> int64_t {
+        const int64_t num = (m - 1) * ca.f0 + m * i * ca.df;
+        return num % ca.df == 0 ? num / ca.df : (2 * num + ca.df) / (2 * ca.df);
+    };
+    int32_t i_max = -1;
+    {
+        int64_t lo = 0, hi = ca.K - 1;
+        while (lo <= hi) {
+            const int64_t mid = (lo + hi) / 2;
+            if (centre_h(prm->h_min, mid) + ca.dk <= ca.K - 1) { i_max = (int32_t)mid; lo = mid + 1; }
+            else hi = mid - 1;
+        }
+        if (i_max > ca.K - 1 - ca.dk) i_max = ca.K - 1 - ca.dk;
+    }
+    const int bw = ca.b_hi - ca.b_lo + 1;
+    if (ca.K <= 4095 && bw <= 254) {
+        const size_t lds = (size_t)ca.kpad * 4 + (size_t)(ca.kpad + 4) * 4;
+        switch (ca.dk) {
+#define DDHF_COMB_CASE(D)                                                                       \
+    case D:                                                                                     \
+        hipLaunchKernelGGL(k_comb_fast<D>, dim3((unsigned)n_active), dim3(kCombThreads), lds, s, \
+                           power, n_active, ca, i_max, sf, snr_best, bin_best, snr_all, n_dev); \
+        break;
+            DDHF_COMB_CASE(0)
+            DDHF_COMB_CASE(1)
+            DDHF_COMB_CASE(2)
+            DDHF_COMB_CASE(3)
+            DDHF_COMB_CASE(4)
+#undef DDHF_COMB_CASE
+            default:
+                hipLaunchKernelGGL(k_comb_fast<-1>, dim3((unsigned)n_active), dim3(kCombThreads),
+                                   lds, s, power, n_active, ca, i_max, sf, snr_best, bin_best,
+                                   snr_all, n_dev);
+        }
+        DDHF_LAUNCH_CHECK();
+        return DDHF_OK;
+    }
     const size_t lds = comb_lds_bytes(ca);
     if (lds > 64 * 1024) return DDHF_EINVAL;
-    hipStream_t s = as_stream(stream);
-    static bool attr_set = false;
-    if (!attr_set) {
-        (void)hipFuncSetAttribute((const void*)k_comb, hipFuncAttributeMaxDynamicSharedMemorySize,
-                            64 * 1024);
-        attr_set = true;
-    }
     hipLaunchKernelGGL(k_comb, dim3((unsigned)n_active), dim3(kCombThreads), lds, s, power,
-                       n_active, ca, sf, snr_best, bin_best, snr_all);
+                       n_active, ca, sf, snr_best, bin_best, snr_all, n_dev);
     DDHF_LAUNCH_CHECK();
     return DDHF_OK;
+}
+}  // namespace ddhf
+
+extern "C" int ddhf_comb_score(const float* power, int32_t n_active, const ddhf_grid_t* grid,
+                               const ddhf_params_t* prm, float* sf, float* snr_best,
+                               int32_t* bin_best, float* snr_all, void* stream) {
+    return comb_run(power, n_active, nullptr, grid, prm, sf, snr_best, bin_best, snr_all,
+                    as_stream(stream));
 }

@@ -79,4 +79,27 @@ int scan_exclusive_u32(const uint32_t* in, uint32_t* out, int64_t n, void* ws, h
 // Fill n u32 with a value (graph-capture safe, unlike hipMemsetAsync).
 int fill_u32(uint32_t* p, uint32_t v, int64_t n, hipStream_t s);
 
+// Stable LSD radix sort of (u32 key, u32 value) pairs on the low nbits of the
+// keys; the count is n_bound, or *n_dev if given.  Data ping-pongs between
+// (k0, v0) and (k1, v1); *in_first tells where the result is.
+size_t radix_ws_bytes(int64_t n);
+int sort_pairs_u32(uint32_t* k0, uint32_t* v0, uint32_t* k1, uint32_t* v1, int64_t n_bound,
+                   const int32_t* n_dev, int nbits, void* ws, hipStream_t s, bool* in_first);
+int bits_for(uint64_t max_value);
+
+// Launches with an optional device-side count (kernels skip items at or past
+// *n_dev; grids are sized for the host bound n_active).
+int ndft_run(const int32_t* row_ptr, const uint32_t* t_rel, const float* a, const int32_t* active,
+             int32_t n_active, const int32_t* n_dev, int64_t n_events, const ddhf_grid_t* grid,
+             float* power, const ddhf_launch_t* launch, void* ws, size_t ws_bytes, hipStream_t s);
+int comb_run(const float* power, int32_t n_active, const int32_t* n_dev, const ddhf_grid_t* grid,
+             const ddhf_params_t* prm, float* sf, float* snr_best, int32_t* bin_best,
+             float* snr_all, hipStream_t s);
+// row_ptr may be null: every listed pixel is taken to satisfy n_min.
+int detect_run(const int32_t* active, const int32_t* row_ptr, const float* sf,
+               const float* snr_best, const int32_t* bin_best, int32_t n_active,
+               const int32_t* n_dev, int32_t W, int32_t H, const ddhf_grid_t* grid,
+               const ddhf_params_t* prm, uint8_t* mask, int32_t* labels, ddhf_box_t* boxes,
+               int32_t max_boxes, int32_t* n_boxes, void* ws, size_t ws_bytes, hipStream_t s);
+
 }  // namespace ddhf

@@ -81,11 +81,11 @@ struct MaskArgs {
 __global__ void k_det_mask(const int32_t* __restrict__ active, const int32_t* __restrict__ row_ptr,
                            const float* __restrict__ sf, const float* __restrict__ snr,
                            const int32_t* __restrict__ bin, int32_t n_active, MaskArgs ma,
-                           uint8_t* __restrict__ mask, int32_t* __restrict__ labels, DetectWs d) {
+                           uint8_t* __restrict__ mask, int32_t* __restrict__ labels, DetectWs d, const int32_t* __restrict__ n_dev) {
     const int32_t u = blockIdx.x * blockDim.x + threadIdx.x;
-    if (u >= n_active) return;
+    if (u >= n_active || (n_dev && u >= *n_dev)) return;
     const int32_t q = active[u];
-    const int32_t cnt = row_ptr[q + 1] - row_ptr[q];
+    const int32_t cnt = row_ptr ? row_ptr[q + 1] - row_ptr[q] : ma.n_min;
     if (cnt >= ma.n_min && sf[u] <= ma.tau_sf && snr[u] >= ma.tau_comb) {
         mask[q] = 1;
         labels[q] = q;
@@ -100,9 +100,9 @@ __global__ void k_det_mask(const int32_t* __restrict__ active, const int32_t* __
 }
 
 __global__ void k_det_union(const int32_t* __restrict__ active, int32_t n_active, int32_t W,
-                            int32_t H, const uint8_t* __restrict__ mask, int32_t* labels) {
+                            int32_t H, const uint8_t* __restrict__ mask, int32_t* labels, const int32_t* __restrict__ n_dev) {
     const int32_t u = blockIdx.x * blockDim.x + threadIdx.x;
-    if (u >= n_active) return;
+    if (u >= n_active || (n_dev && u >= *n_dev)) return;
     const int32_t q = active[u];
     if (!mask[q]) return;
     const int32_t x = q % W, y = q / W;
@@ -118,39 +118,78 @@ __global__ void k_det_union(const int32_t* __restrict__ active, int32_t n_active
 }
 
 __global__ void k_det_compress(const int32_t* __restrict__ active, int32_t n_active,
-                               const uint8_t* __restrict__ mask, int32_t* labels) {
+                               const uint8_t* __restrict__ mask, int32_t* labels, const int32_t* __restrict__ n_dev) {
     const int32_t u = blockIdx.x * blockDim.x + threadIdx.x;
-    if (u >= n_active) return;
+    if (u >= n_active || (n_dev && u >= *n_dev)) return;
     const int32_t q = active[u];
     if (!mask[q]) return;
     const int32_t r = uf_find(labels, q);
     __hip_atomic_store(&labels[q], r, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-__global__ void k_det_accum(const int32_t* __restrict__ active, const float* __restrict__ snr,
-                            int32_t n_active, int32_t W, const uint8_t* __restrict__ mask,
-                            const int32_t* __restrict__ labels, DetectWs d) {
+// Box accumulation.  Large components make many lanes share one root, so a
+// wavefront whose mask lanes all share the first lane's root reduces in
+// registers and issues one atomic per field; other waves use per-lane atomics.
+__global__ __launch_bounds__(256) void k_det_accum(const int32_t* __restrict__ active,
+                                                   const float* __restrict__ snr, int32_t n_active,
+                                                   int32_t W, const uint8_t* __restrict__ mask,
+                                                   const int32_t* __restrict__ labels,
+                                                   DetectWs d, const int32_t* __restrict__ n_dev) {
     const int32_t u = blockIdx.x * blockDim.x + threadIdx.x;
-    if (u >= n_active) return;
-    const int32_t q = active[u];
-    if (!mask[q]) return;
-    const int32_t r = labels[q];
-    const int32_t x = q % W, y = q / W;
+    int32_t q = -1, r = -1;
+    if (u < n_active && !(n_dev && u >= *n_dev)) {
+        q = active[u];
+        if (mask[q]) r = labels[q];
+        else q = -1;
+    }
+    const bool on = r >= 0;
+    const uint64_t pend = __ballot(on);
+    if (pend == 0) return;
+    const int leader = __ffsll((long long)pend) - 1;
+    const int32_t r0 = __shfl(r, leader, 64);
+    const uint64_t same = __ballot(on && r == r0);
+    const int32_t x = on ? q % W : 0x7FFFFFFF, y = on ? q / W : 0x7FFFFFFF;
+    const unsigned long long key =
+        on ? (((unsigned long long)__float_as_uint(snr[u]) << 32) |
+              (unsigned long long)(0xFFFFFFFFu - (uint32_t)q))
+           : 0ull;
+    if (same == pend) {
+        int32_t x0 = x, y0 = y, x1 = on ? x : -1, y1 = on ? y : -1, c = on ? 1 : 0;
+        unsigned long long k = key;
+#pragma unroll
+        for (int dd = 32; dd >= 1; dd >>= 1) {
+            x0 = min(x0, __shfl_xor(x0, dd, 64));
+            y0 = min(y0, __shfl_xor(y0, dd, 64));
+            x1 = max(x1, __shfl_xor(x1, dd, 64));
+            y1 = max(y1, __shfl_xor(y1, dd, 64));
+            c += __shfl_xor(c, dd, 64);
+            const unsigned long long o = __shfl_xor(k, dd, 64);
+            k = o > k ? o : k;
+        }
+        if (__lane_id() == leader) {
+            atomicMin(&d.x0[r0], x0);
+            atomicMin(&d.y0[r0], y0);
+            atomicMax(&d.x1[r0], x1);
+            atomicMax(&d.y1[r0], y1);
+            atomicAdd(&d.npx[r0], c);
+            atomicMax(&d.rep[r0], k);
+        }
+        return;
+    }
+    if (!on) return;
     atomicMin(&d.x0[r], x);
     atomicMin(&d.y0[r], y);
     atomicMax(&d.x1[r], x);
     atomicMax(&d.y1[r], y);
     atomicAdd(&d.npx[r], 1);
-    const unsigned long long key =
-        ((unsigned long long)__float_as_uint(snr[u]) << 32) | (unsigned long long)(0xFFFFFFFFu - (uint32_t)q);
     atomicMax(&d.rep[r], key);
 }
 
 __global__ void k_det_collect(const int32_t* __restrict__ active, int32_t n_active,
                               const uint8_t* __restrict__ mask, const int32_t* __restrict__ labels,
-                              int32_t a_min, DetectWs d) {
+                              int32_t a_min, DetectWs d, const int32_t* __restrict__ n_dev) {
     const int32_t u = blockIdx.x * blockDim.x + threadIdx.x;
-    if (u >= n_active) return;
+    if (u >= n_active || (n_dev && u >= *n_dev)) return;
     const int32_t q = active[u];
     if (!mask[q] || labels[q] != q) return;
     const int64_t area = (int64_t)(d.x1[q] - d.x0[q] + 1) * (int64_t)(d.y1[q] - d.y0[q] + 1);
@@ -423,23 +462,22 @@ extern "C" int ddhf_detect_workspace_size(int32_t W, int32_t H, size_t* bytes) {
     return DDHF_OK;
 }
 
-extern "C" int ddhf_detect(const int32_t* active, const int32_t* row_ptr, const float* sf,
-                           const float* snr_best, const int32_t* bin_best, int32_t n_active,
-                           int32_t W, int32_t H, const ddhf_grid_t* grid,
-                           const ddhf_params_t* prm, uint8_t* mask, int32_t* labels,
-                           ddhf_box_t* boxes, int32_t max_boxes, int32_t* n_boxes, void* ws,
-                           size_t ws_bytes, void* stream) {
+namespace ddhf {
+int detect_run(const int32_t* active, const int32_t* row_ptr, const float* sf,
+               const float* snr_best, const int32_t* bin_best, int32_t n_active,
+               const int32_t* n_dev, int32_t W, int32_t H, const ddhf_grid_t* grid,
+               const ddhf_params_t* prm, uint8_t* mask, int32_t* labels, ddhf_box_t* boxes,
+               int32_t max_boxes, int32_t* n_boxes, void* ws, size_t ws_bytes, hipStream_t s) {
     if (!grid || !prm || W <= 0 || H <= 0 || (int64_t)W * H >= INT32_MAX || n_active < 0 ||
         max_boxes < 0 || !mask || !labels || !n_boxes || !ws || (max_boxes > 0 && !boxes))
         return DDHF_EINVAL;
-    if (n_active > 0 && (!active || !row_ptr || !sf || !snr_best || !bin_best)) return DDHF_EINVAL;
+    if (n_active > 0 && (!active || !sf || !snr_best || !bin_best)) return DDHF_EINVAL;
     if (!(prm->alpha >= 0.0f) || grid->df <= 0) return DDHF_EINVAL;
     const int64_t npix = (int64_t)W * H;
     Arena ar(ws, ws_bytes);
     DetectWs d;
     detect_layout(ar, npix, &d);
     if (!ar.fits()) return DDHF_ENOSPACE;
-    hipStream_t s = as_stream(stream);
     hipLaunchKernelGGL(k_det_init, dim3(blocks_for(npix, 256)), dim3(256), 0, s, mask, labels, npix,
                        d.ctr);
     DDHF_LAUNCH_CHECK();
@@ -447,29 +485,34 @@ extern "C" int ddhf_detect(const int32_t* active, const int32_t* row_ptr, const 
         MaskArgs ma{prm->tau_sf, prm->tau_comb, prm->n_min};
         const dim3 gb(blocks_for(n_active, 256));
         hipLaunchKernelGGL(k_det_mask, gb, dim3(256), 0, s, active, row_ptr, sf, snr_best, bin_best,
-                           n_active, ma, mask, labels, d);
+                           n_active, ma, mask, labels, d, n_dev);
         DDHF_LAUNCH_CHECK();
-        hipLaunchKernelGGL(k_det_union, gb, dim3(256), 0, s, active, n_active, W, H, mask, labels);
+        hipLaunchKernelGGL(k_det_union, gb, dim3(256), 0, s, active, n_active, W, H, mask, labels, n_dev);
         DDHF_LAUNCH_CHECK();
-        hipLaunchKernelGGL(k_det_compress, gb, dim3(256), 0, s, active, n_active, mask, labels);
+        hipLaunchKernelGGL(k_det_compress, gb, dim3(256), 0, s, active, n_active, mask, labels, n_dev);
         DDHF_LAUNCH_CHECK();
         hipLaunchKernelGGL(k_det_accum, gb, dim3(256), 0, s, active, snr_best, n_active, W, mask,
-                           labels, d);
+                           labels, d, n_dev);
         DDHF_LAUNCH_CHECK();
         hipLaunchKernelGGL(k_det_collect, gb, dim3(256), 0, s, active, n_active, mask, labels,
-                           prm->a_min, d);
+                           prm->a_min, d, n_dev);
         DDHF_LAUNCH_CHECK();
-    }
-    static bool attr_set = false;
-    if (!attr_set) {
-        (void)hipFuncSetAttribute((const void*)k_det_merge,
-                                  hipFuncAttributeMaxDynamicSharedMemorySize,
-                                  (int)merge_lds_bytes());
-        attr_set = true;
     }
     hipLaunchKernelGGL(k_det_merge, dim3(1), dim3(kMergeThreads), merge_lds_bytes(), s, d,
                        (double)prm->alpha, grid->f0, grid->df, grid->mode, grid->T_w_us, boxes,
                        max_boxes, n_boxes);
     DDHF_LAUNCH_CHECK();
     return DDHF_OK;
+}
+}  // namespace ddhf
+
+extern "C" int ddhf_detect(const int32_t* active, const int32_t* row_ptr, const float* sf,
+                           const float* snr_best, const int32_t* bin_best, int32_t n_active,
+                           int32_t W, int32_t H, const ddhf_grid_t* grid,
+                           const ddhf_params_t* prm, uint8_t* mask, int32_t* labels,
+                           ddhf_box_t* boxes, int32_t max_boxes, int32_t* n_boxes, void* ws,
+                           size_t ws_bytes, void* stream) {
+    if (n_active > 0 && !row_ptr) return DDHF_EINVAL;
+    return detect_run(active, row_ptr, sf, snr_best, bin_best, n_active, nullptr, W, H, grid, prm,
+                      mask, labels, boxes, max_boxes, n_boxes, ws, ws_bytes, as_stream(stream));
 }

@@ -200,7 +200,7 @@ struct RadixWs {
     void* scan_ws;
 };
 
-static size_t radix_ws_bytes(int64_t n) {
+size_t radix_ws_bytes(int64_t n) {
     int64_t n_tiles = (n + kRadixTile - 1) / kRadixTile;
     if (n_tiles < 1) n_tiles = 1;
     return 2 * align_up((size_t)n_tiles * 256 * sizeof(uint32_t)) + scan_ws_bytes(n_tiles * 256);
@@ -218,7 +218,7 @@ static RadixWs radix_ws_take(Arena& ar, int64_t n) {
 
 // Sorts bits [bit0, bit0 + nbits) of the keys.  Data ping-pongs between
 // (k0, v0) and (k1, v1); *in_first tells where the result ended up.
-static int radix_sort_pairs(uint32_t* k0, uint32_t* v0, uint32_t* k1, uint32_t* v1,
+int radix_sort_pairs(uint32_t* k0, uint32_t* v0, uint32_t* k1, uint32_t* v1,
                             int64_t n_bound, const int32_t* n_dev, int bit0, int nbits,
                             const RadixWs& rw, hipStream_t s, bool* in_first) {
     *in_first = true;
@@ -243,7 +243,14 @@ static int radix_sort_pairs(uint32_t* k0, uint32_t* v0, uint32_t* k1, uint32_t* 
     return DDHF_OK;
 }
 
-static int bits_for(uint64_t max_value) {
+int sort_pairs_u32(uint32_t* k0, uint32_t* v0, uint32_t* k1, uint32_t* v1, int64_t n_bound,
+                   const int32_t* n_dev, int nbits, void* ws, hipStream_t s, bool* in_first) {
+    Arena ar(ws, radix_ws_bytes(n_bound));
+    RadixWs rw = radix_ws_take(ar, n_bound);
+    return radix_sort_pairs(k0, v0, k1, v1, n_bound, n_dev, 0, nbits, rw, s, in_first);
+}
+
+int bits_for(uint64_t max_value) {
     int b = 0;
     while (b < 32 && (max_value >> b) != 0) ++b;
     return b;
@@ -263,39 +270,54 @@ __global__ void k_counters_init(ddhf_counters_t* c, int64_t n) {
     }
 }
 
-__device__ __forceinline__ void wave_count(unsigned long long* dst, bool pred) {
-    uint64_t b = __ballot(pred);
-    if (__lane_id() == 0 && b) atomicAdd(dst, (unsigned long long)__popcll(b));
-}
+constexpr int kPrepThreads = 256;
+constexpr int kPrepItems = 8;
 
-__global__ __launch_bounds__(256) void k_prepare(
+// Window filter and sort keys.  Each thread handles kPrepItems events; the
+// five event counters are reduced per workgroup and added with one atomic each.
+__global__ __launch_bounds__(kPrepThreads) void k_prepare(
     const uint16_t* __restrict__ x, const uint16_t* __restrict__ y, const int8_t* __restrict__ p,
     const int64_t* __restrict__ t, int64_t n, int32_t W, int32_t H, int64_t t0, int64_t T_w,
     uint32_t* __restrict__ key_pix, uint32_t* __restrict__ key_t, uint32_t* __restrict__ vals,
     ddhf_counters_t* counters) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const bool in = i < n;
-    int cat = 0;  // 1 kept, 2 window, 3 sensor, 4 polarity
-    bool unsorted = false;
-    if (in) {
-        const int64_t ti = t[i];
-        const bool win = ti >= t0 && ti < t0 + T_w;
-        const bool sen = x[i] < W && y[i] < H;
-        const int8_t pi = p[i];
-        const bool pol = pi >= -1 && pi <= 1;
-        cat = !win ? 2 : (!sen ? 3 : (!pol ? 4 : 1));
-        const uint32_t npix = (uint32_t)W * (uint32_t)H;
-        key_pix[i] = cat == 1 ? (uint32_t)y[i] * (uint32_t)W + x[i] : npix;
-        if (key_t) key_t[i] = cat == 1 ? (uint32_t)(ti - t0) : 0u;
-        vals[i] = (uint32_t)i;
-        unsorted = i > 0 && ti < t[i - 1];
+    __shared__ uint32_t red[5][kPrepThreads / kWave];
+    uint32_t c[5] = {0, 0, 0, 0, 0};  // kept, window, sensor, polarity, unsorted
+    const uint32_t npix = (uint32_t)W * (uint32_t)H;
+    const int64_t base = (int64_t)blockIdx.x * kPrepThreads * kPrepItems + threadIdx.x;
+#pragma unroll
+    for (int it = 0; it < kPrepItems; ++it) {
+        const int64_t i = base + (int64_t)it * kPrepThreads;
+        if (i < n) {
+            const int64_t ti = t[i];
+            const bool win = ti >= t0 && ti < t0 + T_w;
+            const bool sen = x[i] < W && y[i] < H;
+            const int8_t pi = p[i];
+            const bool pol = pi >= -1 && pi <= 1;
+            const int cat = !win ? 1 : (!sen ? 2 : (!pol ? 3 : 0));
+            c[cat] += 1u;
+            key_pix[i] = cat == 0 ? (uint32_t)y[i] * (uint32_t)W + x[i] : npix;
+            if (key_t) key_t[i] = cat == 0 ? (uint32_t)(ti - t0) : 0u;
+            vals[i] = (uint32_t)i;
+            if (i > 0 && ti < t[i - 1]) c[4] += 1u;
+        }
     }
-    if (counters) {
-        wave_count((unsigned long long*)&counters->n_kept, cat == 1);
-        wave_count((unsigned long long*)&counters->out_of_window, cat == 2);
-        wave_count((unsigned long long*)&counters->out_of_sensor, cat == 3);
-        wave_count((unsigned long long*)&counters->bad_polarity, cat == 4);
-        wave_count((unsigned long long*)&counters->time_unsorted, unsorted);
+    if (!counters) return;
+    const int w = threadIdx.x / kWave;
+#pragma unroll
+    for (int k = 0; k < 5; ++k) {
+        const uint32_t s = wave_sum(c[k]);
+        if (__lane_id() == 0) red[k][w] = s;
+    }
+    __syncthreads();
+    if (threadIdx.x < 5) {
+        uint32_t s = 0;
+        for (int q = 0; q < kPrepThreads / kWave; ++q) s += red[threadIdx.x][q];
+        unsigned long long* dst = threadIdx.x == 0 ? (unsigned long long*)&counters->n_kept
+                                : threadIdx.x == 1 ? (unsigned long long*)&counters->out_of_window
+                                : threadIdx.x == 2 ? (unsigned long long*)&counters->out_of_sensor
+                                : threadIdx.x == 3 ? (unsigned long long*)&counters->bad_polarity
+                                                   : (unsigned long long*)&counters->time_unsorted;
+        if (s) atomicAdd(dst, (unsigned long long)s);
     }
 }
 
@@ -395,7 +417,8 @@ extern "C" int ddhf_build_pixel_index(const uint16_t* x, const uint16_t* y, cons
         DDHF_LAUNCH_CHECK();
     }
     if (n > 0) {
-        hipLaunchKernelGGL(k_prepare, dim3(blocks_for(n, 256)), dim3(256), 0, s, x, y, p, t_us, n,
+        hipLaunchKernelGGL(k_prepare, dim3(blocks_for(n, kPrepThreads * kPrepItems)),
+                           dim3(kPrepThreads), 0, s, x, y, p, t_us, n,
                            W, H, t0_us, T_w_us, key_pix, key_t, vals, counters);
         DDHF_LAUNCH_CHECK();
     }

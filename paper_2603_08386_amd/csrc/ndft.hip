@@ -9,6 +9,15 @@
 // and the step phasor w = exp(i 2 pi S / Q) (FP64 sin/cos, rounded to FP32).
 // For each event every lane forms its exact anchor residue (A + l D) mod Q,
 // one FP32 sin/cos, and then walks its BPL bins by complex rotation with w.
+//
+// Launch forms.  Work is a list of units (pixel, bin tile, event range):
+//   plain       one wavefront per (pixel, tile), units implied by blockIdx;
+//   listed      one wavefront per listed unit (pixels split into chunks);
+//   persistent  a fixed grid of wavefronts pops units from a device counter.
+// Pixels with more than split_events events are cut into balanced chunks whose
+// complex partial spectra go to the workspace; a combine kernel adds them in
+// chunk order (deterministic) and forms the power.  Units are listed in the
+// order of the active list, so a cost-ordered active list runs heaviest first.
 #include "ddhf_internal.h"
 
 namespace ddhf {
@@ -54,93 +63,452 @@ __device__ __forceinline__ void cis_rev(float rev, float& c, float& s) {
     sincospif(2.0f * rev, &s, &c);
 }
 
+struct Unit {
+    int32_t u, wt, beg, end, slot, pad0, pad1, pad2;
+};
+
+struct Split {
+    int32_t u, n_chunks, slot0, pad;
+};
+
+enum { kModePlain = 0, kModeList = 1, kModeQueue = 2 };
+
+struct WorkDev {
+    const Unit* units;
+    const int32_t* n_units;  // device count
+    int32_t* counter;        // queue head
+    float* partials;         // [slot][tile bin][re, im]
+    const int32_t* n_dev;    // plain form: device count of active pixels (nullable)
+};
+
+// Finds the next unit of this wavefront.  Returns false when there is none.
+template <int MODE>
+__device__ __forceinline__ bool next_unit(const WorkDev& wk, const int32_t* row_ptr,
+                                          const int32_t* active, int32_t n_active, int n_wtiles,
+                                          int64_t& iter, Unit& un) {
+    if (MODE == kModePlain) {
+        if (iter > 0) return false;
+        const int64_t unit = (int64_t)blockIdx.x;
+        un.u = (int32_t)(unit / n_wtiles);
+        un.wt = (int)(unit % n_wtiles);
+        const int32_t na = wk.n_dev ? *wk.n_dev : n_active;
+        if (un.u >= na || un.u >= n_active) return false;
+        const int32_t q = active[un.u];
+        un.beg = row_ptr[q];
+        un.end = row_ptr[q + 1];
+        un.slot = -1;
+        ++iter;
+        return true;
+    }
+    int64_t id;
+    if (MODE == kModeList) {
+        if (iter > 0) return false;
+        id = blockIdx.x;
+    } else {
+        int32_t v = 0;
+        if (threadIdx.x == 0) v = atomicAdd(wk.counter, 1);
+        id = __shfl(v, 0, 64);
+    }
+    ++iter;
+    if (id >= *wk.n_units) return false;
+    un = wk.units[id];
+    return true;
+}
+
 struct EvStage {
     uint32_t A, D;
     float a, wc, ws;
 };
 
-template <int BPL>
+// Stages events [c0, c0 + 64) of a unit: exact residues and step phasor.
+__device__ __forceinline__ void stage_event(EvStage* st, int lane, int32_t c0, int32_t end,
+                                            const uint32_t* t_rel, const float* av,
+                                            uint64_t f_tile, const GridDev& g, uint32_t step_mul) {
+    const int32_t e = c0 + lane;
+    if (e < end) {
+        const uint64_t t = t_rel[e];
+        EvStage s;
+        s.A = (uint32_t)((f_tile * t) % g.Q);
+        s.D = (uint32_t)(((uint64_t)g.df * t) % g.Q);
+        const uint32_t S = (uint32_t)(((uint64_t)s.D * step_mul) % g.Q);
+        double rs = (double)S * g.invQ;
+        if (rs >= 0.5) rs -= 1.0;
+        double sn, cs;
+        sincospi(2.0 * rs, &sn, &cs);
+        s.wc = (float)cs;
+        s.ws = (float)sn;
+        s.a = av[e];
+        st[lane] = s;
+    }
+}
+
+template <int BPL, int MODE>
 __global__ __launch_bounds__(64) void k_ndft_valu(const int32_t* __restrict__ row_ptr,
                                                   const uint32_t* __restrict__ t_rel,
                                                   const float* __restrict__ av,
                                                   const int32_t* __restrict__ active,
                                                   int32_t n_active, GridDev g, int n_tiles,
-                                                  float* __restrict__ power) {
+                                                  float* __restrict__ power, WorkDev wk) {
     __shared__ EvStage st[64];
     const int lane = threadIdx.x;
-    const int64_t unit = (int64_t)blockIdx.x;
-    const int32_t u = (int32_t)(unit / n_tiles);
-    const int tile = (int)(unit % n_tiles);
-    if (u >= n_active) return;
-    const int32_t q = active[u];
-    const int32_t beg = row_ptr[q], end = row_ptr[q + 1];
-    const int tile_base = tile * 64 * BPL;
-    const uint64_t f_tile = (uint64_t)(g.f0 + (int64_t)tile_base * g.df);
     const double Qd = (double)g.Q;
-
-    float re[BPL], im[BPL];
+    int64_t iter = 0;
+    Unit un;
+    while (next_unit<MODE>(wk, row_ptr, active, n_active, n_tiles, iter, un)) {
+        const int tile_base = un.wt * 64 * BPL;
+        const uint64_t f_tile = (uint64_t)(g.f0 + (int64_t)tile_base * g.df);
+        float re[BPL], im[BPL];
 #pragma unroll
-    for (int m = 0; m < BPL; ++m) { re[m] = 0.0f; im[m] = 0.0f; }
-
-    for (int32_t c0 = beg; c0 < end; c0 += 64) {
-        const int32_t e = c0 + lane;
-        if (e < end) {
-            const uint64_t t = t_rel[e];
-            EvStage s;
-            s.A = (uint32_t)((f_tile * t) % g.Q);
-            s.D = (uint32_t)(((uint64_t)g.df * t) % g.Q);
-            const uint32_t S = (uint32_t)(((uint64_t)s.D * 64u) % g.Q);
-            double rs = (double)S * g.invQ;
-            if (rs >= 0.5) rs -= 1.0;
-            double sn, cs;
-            sincospi(2.0 * rs, &sn, &cs);
-            s.wc = (float)cs;
-            s.ws = (float)sn;
-            s.a = av[e];
-            st[lane] = s;
+        for (int m = 0; m < BPL; ++m) { re[m] = 0.0f; im[m] = 0.0f; }
+        for (int32_t c0 = un.beg; c0 < un.end; c0 += 64) {
+            stage_event(st, lane, c0, un.end, t_rel, av, f_tile, g, 64u);
+            __syncthreads();
+            const int ne = (un.end - c0) < 64 ? (un.end - c0) : 64;
+            for (int k = 0; k < ne; ++k) {
+                const EvStage s = st[k];
+                const double x = (double)lane * (double)s.D + (double)s.A;
+                const uint32_t r = mod_q_small(x, Qd, g.invQ);
+                double rv = (double)r * g.invQ;
+                if (rv >= 0.5) rv -= 1.0;
+                float c, sn;
+                cis_rev((float)rv, c, sn);
+                float zr = s.a * c, zi = s.a * sn;
+#pragma unroll
+                for (int m = 0; m < BPL; ++m) {
+                    re[m] += zr;
+                    im[m] += zi;
+                    const float nr = zr * s.wc - zi * s.ws;
+                    const float ni = zr * s.ws + zi * s.wc;
+                    zr = nr;
+                    zi = ni;
+                }
+            }
+            __syncthreads();
         }
-        __syncthreads();
-        const int ne = (end - c0) < 64 ? (end - c0) : 64;
-        for (int k = 0; k < ne; ++k) {
-            const EvStage s = st[k];
-            const double x = (double)lane * (double)s.D + (double)s.A;
-            const uint32_t r = mod_q_small(x, Qd, g.invQ);
-            double rv = (double)r * g.invQ;
-            if (rv >= 0.5) rv -= 1.0;
-            float c, sn;
-            cis_rev((float)rv, c, sn);
-            float zr = s.a * c, zi = s.a * sn;
+        if (un.slot < 0) {
+            float* out = power + (int64_t)un.u * g.K;
 #pragma unroll
             for (int m = 0; m < BPL; ++m) {
-                re[m] += zr;
-                im[m] += zi;
-                const float nr = zr * s.wc - zi * s.ws;
-                const float ni = zr * s.ws + zi * s.wc;
-                zr = nr;
-                zi = ni;
+                const int j = tile_base + lane + 64 * m;
+                if (j < g.K) out[j] = re[m] * re[m] + im[m] * im[m];
             }
-        }
-        __syncthreads();
-    }
-    float* out = power + (int64_t)u * g.K;
+        } else {
+            float2* part = (float2*)wk.partials + (int64_t)un.slot * (64 * BPL);
 #pragma unroll
-    for (int m = 0; m < BPL; ++m) {
-        const int j = tile_base + lane + 64 * m;
-        if (j < g.K) out[j] = re[m] * re[m] + im[m] * im[m];
+            for (int m = 0; m < BPL; ++m) part[lane + 64 * m] = make_float2(re[m], im[m]);
+        }
     }
 }
 
-template <int BPL>
-static int launch_valu(const int32_t* row_ptr, const uint32_t* t_rel, const float* a,
-                       const int32_t* active, int32_t n_active, const GridDev& g, float* power,
-                       hipStream_t s) {
-    const int n_tiles = (g.K + 64 * BPL - 1) / (64 * BPL);
-    const int64_t units = (int64_t)n_active * n_tiles;
-    if (units <= 0) return DDHF_OK;
-    if (units > 0x7FFFFFFFLL) return DDHF_EINVAL;
-    hipLaunchKernelGGL(k_ndft_valu<BPL>, dim3((unsigned)units), dim3(64), 0, s, row_ptr, t_rel, a,
-                       active, n_active, g, n_tiles, power);
+// ---------------------------------------------------------------------------
+// MFMA kernel (factorised).  With bins j = 32 b + s of a wave's tile,
+//   F[32 b + s] = sum_e a_e exp(i 2 pi (A_e + 32 b D_e) / Q) exp(i 2 pi s D_e / Q)
+//              = sum_e U[b, e] V[e, s],
+// a complex contraction over the events.  Each v_mfma_f32_32x32x2_f32 takes one
+// event as its k = 2 slice: A[i][0..1] = (Re U, Im U) of row i, and
+// B = (Re V, -Im V) for the real part, (Im V, Re V) for the imaginary part.
+// Lane l (row / column l mod 32) forms the exact residues (A_e + 32 l D_e) and
+// (l D_e) mod Q, one sin/cos each; further 32-row tiles of U follow by
+// multiplying with the exact step phasor exp(i 2 pi (1024 D_e mod Q) / Q).
+// Accumulator layout (32x32 block): element r of lane l is row
+// 8 (r / 4) + 4 (l / 32) + r % 4, column l % 32.
+// ---------------------------------------------------------------------------
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+
+template <int NB, int MODE>
+__global__ __launch_bounds__(64) void k_ndft_mfma(const int32_t* __restrict__ row_ptr,
+                                                  const uint32_t* __restrict__ t_rel,
+                                                  const float* __restrict__ av,
+                                                  const int32_t* __restrict__ active,
+                                                  int32_t n_active, GridDev g, int n_wtiles,
+                                                  float* __restrict__ power, WorkDev wk) {
+    __shared__ EvStage st[64];
+    const int lane = threadIdx.x;
+    const double Qd = (double)g.Q;
+    const int r32 = lane & 31;
+    const bool upper = lane >= 32;
+    int64_t iter = 0;
+    Unit un;
+    while (next_unit<MODE>(wk, row_ptr, active, n_active, n_wtiles, iter, un)) {
+        const int tile_base = un.wt * NB * 1024;
+        const uint64_t f_tile = (uint64_t)(g.f0 + (int64_t)tile_base * g.df);
+        f32x16 cre[NB], cim[NB];
+#pragma unroll
+        for (int b = 0; b < NB; ++b) {
+#pragma unroll
+            for (int r = 0; r < 16; ++r) { cre[b][r] = 0.0f; cim[b][r] = 0.0f; }
+        }
+        for (int32_t c0 = un.beg; c0 < un.end; c0 += 64) {
+            stage_event(st, lane, c0, un.end, t_rel, av, f_tile, g, 1024u);
+            __syncthreads();
+            const int ne = (un.end - c0) < 64 ? (un.end - c0) : 64;
+            for (int k = 0; k < ne; ++k) {
+                const EvStage s = st[k];
+                const double D = (double)s.D;
+                // column phasor V(s = r32)
+                const uint32_t rv = mod_q_small((double)r32 * D, Qd, g.invQ);
+                double fv = (double)rv * g.invQ;
+                if (fv >= 0.5) fv -= 1.0;
+                float vc, vs;
+                cis_rev((float)fv, vc, vs);
+                // row phasor U(b = r32) of the first 32-row tile
+                const uint32_t ru = mod_q_small((double)s.A + 32.0 * (double)r32 * D, Qd, g.invQ);
+                double fu = (double)ru * g.invQ;
+                if (fu >= 0.5) fu -= 1.0;
+                float uc, us;
+                cis_rev((float)fu, uc, us);
+                uc *= s.a;
+                us *= s.a;
+                const float bre = upper ? -vs : vc;
+                const float bim = upper ? vc : vs;
+#pragma unroll
+                for (int b = 0; b < NB; ++b) {
+                    const float aop = upper ? us : uc;
+                    cre[b] = __builtin_amdgcn_mfma_f32_32x32x2f32(aop, bre, cre[b], 0, 0, 0);
+                    cim[b] = __builtin_amdgcn_mfma_f32_32x32x2f32(aop, bim, cim[b], 0, 0, 0);
+                    if (b + 1 < NB) {
+                        const float nr = uc * s.wc - us * s.ws;
+                        const float ni = uc * s.ws + us * s.wc;
+                        uc = nr;
+                        us = ni;
+                    }
+                }
+            }
+            __syncthreads();
+        }
+        const int col = lane & 31;
+        const int half = lane >> 5;
+        if (un.slot < 0) {
+            float* out = power + (int64_t)un.u * g.K;
+#pragma unroll
+            for (int b = 0; b < NB; ++b) {
+#pragma unroll
+                for (int r = 0; r < 16; ++r) {
+                    const int row = b * 32 + 8 * (r >> 2) + 4 * half + (r & 3);
+                    const int j = tile_base + row * 32 + col;
+                    if (j < g.K) out[j] = cre[b][r] * cre[b][r] + cim[b][r] * cim[b][r];
+                }
+            }
+        } else {
+            float2* part = (float2*)wk.partials + (int64_t)un.slot * (NB * 1024);
+#pragma unroll
+            for (int b = 0; b < NB; ++b) {
+#pragma unroll
+                for (int r = 0; r < 16; ++r) {
+                    const int row = b * 32 + 8 * (r >> 2) + 4 * half + (r & 3);
+                    part[row * 32 + col] = make_float2(cre[b][r], cim[b][r]);
+                }
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// unit list, split records, combine
+// ---------------------------------------------------------------------------
+__global__ void k_units_count(const int32_t* __restrict__ active, const int32_t* __restrict__ row_ptr,
+                              int32_t n_active, int32_t split, int32_t n_wtiles,
+                              uint32_t* __restrict__ c_units, uint32_t* __restrict__ c_slots,
+                              uint32_t* __restrict__ c_split) {
+    const int32_t u = blockIdx.x * blockDim.x + threadIdx.x;
+    if (u >= n_active) return;
+    const int32_t q = active[u];
+    const int32_t n = row_ptr[q + 1] - row_ptr[q];
+    const int32_t ch = (split > 0 && n > split) ? (n + split - 1) / split : 1;
+    c_units[u] = (uint32_t)(ch * n_wtiles);
+    c_slots[u] = ch > 1 ? (uint32_t)(ch * n_wtiles) : 0u;
+    c_split[u] = ch > 1 ? 1u : 0u;
+}
+
+__global__ void k_units_fill(const int32_t* __restrict__ active, const int32_t* __restrict__ row_ptr,
+                             int32_t n_active, int32_t split, int32_t n_wtiles,
+                             const uint32_t* __restrict__ c_units, const uint32_t* __restrict__ c_slots,
+                             const uint32_t* __restrict__ c_split,
+                             const uint32_t* __restrict__ o_units, const uint32_t* __restrict__ o_slots,
+                             const uint32_t* __restrict__ o_split, Unit* __restrict__ units,
+                             Split* __restrict__ splits, int32_t* __restrict__ totals,
+                             int32_t* __restrict__ counter) {
+    const int32_t u = blockIdx.x * blockDim.x + threadIdx.x;
+    if (u == 0) *counter = 0;
+    if (u >= n_active) return;
+    const int32_t q = active[u];
+    const int32_t b = row_ptr[q], n = row_ptr[q + 1] - b;
+    const int32_t ch = (split > 0 && n > split) ? (n + split - 1) / split : 1;
+    const uint32_t ub = o_units[u];
+    for (int32_t c = 0; c < ch; ++c) {
+        const int32_t cb = b + (int32_t)(((int64_t)n * c) / ch);
+        const int32_t ce = b + (int32_t)(((int64_t)n * (c + 1)) / ch);
+        for (int32_t wt = 0; wt < n_wtiles; ++wt) {
+            Unit un;
+            un.u = u;
+            un.wt = wt;
+            un.beg = cb;
+            un.end = ce;
+            un.slot = ch > 1 ? (int32_t)(o_slots[u] + (uint32_t)(wt * ch + c)) : -1;
+            un.pad0 = un.pad1 = un.pad2 = 0;
+            units[ub + (uint32_t)(c * n_wtiles + wt)] = un;
+        }
+    }
+    if (ch > 1) {
+        Split sp;
+        sp.u = u;
+        sp.n_chunks = ch;
+        sp.slot0 = (int32_t)o_slots[u];
+        sp.pad = 0;
+        splits[o_split[u]] = sp;
+    }
+    if (u == n_active - 1) {
+        totals[0] = (int32_t)(o_units[u] + c_units[u]);
+        totals[1] = (int32_t)(o_split[u] + c_split[u]);
+    }
+}
+
+// One workgroup per (split pixel, tile): sums the chunk partials in chunk order.
+__global__ __launch_bounds__(256) void k_combine(const Split* __restrict__ splits,
+                                                 const int32_t* __restrict__ totals, int32_t n_wtiles,
+                                                 int32_t tile_bins, const float2* __restrict__ partials,
+                                                 int32_t K, float* __restrict__ power) {
+    const int32_t rec = blockIdx.x / n_wtiles;
+    const int32_t wt = blockIdx.x % n_wtiles;
+    if (rec >= totals[1]) return;
+    const Split sp = splits[rec];
+    float* out = power + (int64_t)sp.u * K;
+    for (int jt = threadIdx.x; jt < tile_bins; jt += blockDim.x) {
+        const int j = wt * tile_bins + jt;
+        if (j >= K) continue;
+        float re = 0.0f, im = 0.0f;
+        for (int c = 0; c < sp.n_chunks; ++c) {
+            const float2 v = partials[(int64_t)(sp.slot0 + wt * sp.n_chunks + c) * tile_bins + jt];
+            re += v.x;
+            im += v.y;
+        }
+        out[j] = re * re + im * im;
+    }
+}
+
+struct Plan {
+    int kernel, bpl, nb, split, mode;
+    int tile_bins, n_wtiles;
+    int64_t max_units, max_slots, max_splits;
+};
+
+static bool make_plan(const ddhf_launch_t* launch, int32_t n_active, int64_t n_events, int K,
+                      Plan* p) {
+    p->kernel = launch ? launch->kernel : DDHF_KERNEL_VALU;
+    p->bpl = launch ? launch->bins_per_lane : 32;
+    p->split = launch ? launch->split_events : 0;
+    p->mode = launch && launch->persistent ? kModeQueue : (p->split > 0 ? kModeList : kModePlain);
+    if (p->split < 0) return false;
+    if (p->kernel == DDHF_KERNEL_VALU) {
+        if (p->bpl != 8 && p->bpl != 16 && p->bpl != 32 && p->bpl != 64) return false;
+        p->nb = 0;
+        p->tile_bins = 64 * p->bpl;
+    } else if (p->kernel == DDHF_KERNEL_MFMA) {
+        if (p->bpl != 16 && p->bpl != 32 && p->bpl != 64) return false;
+        p->nb = p->bpl / 16;
+        p->tile_bins = p->nb * 1024;
+    } else {
+        return false;
+    }
+    p->n_wtiles = (K + p->tile_bins - 1) / p->tile_bins;
+    // split pixels have more than `split` events, so their chunks number at most 2 n / split
+    const int64_t chunks = p->split > 0 ? 2 * n_events / p->split + 1 : 0;
+    p->max_units = ((int64_t)n_active + chunks) * p->n_wtiles;
+    p->max_slots = chunks * p->n_wtiles;
+    p->max_splits = p->split > 0 ? (n_events / (p->split + 1) + 1) : 0;
+    if (p->max_splits > n_active) p->max_splits = n_active;
+    return true;
+}
+
+struct PlanWs {
+    uint32_t *c_units, *c_slots, *c_split, *o_units, *o_slots, *o_split;
+    void* scan_ws;
+    Unit* units;
+    Split* splits;
+    float* partials;
+    int32_t* totals;   // [0] units, [1] splits
+    int32_t* counter;
+};
+
+static void plan_layout(Arena& ar, const Plan& p, int32_t n_active, PlanWs* w) {
+    const int64_t na = n_active > 0 ? n_active : 1;
+    w->totals = ar.take<int32_t>(4);
+    w->counter = ar.take<int32_t>(4);
+    if (p.mode == kModePlain) return;
+    w->c_units = ar.take<uint32_t>(na);
+    w->c_slots = ar.take<uint32_t>(na);
+    w->c_split = ar.take<uint32_t>(na);
+    w->o_units = ar.take<uint32_t>(na);
+    w->o_slots = ar.take<uint32_t>(na);
+    w->o_split = ar.take<uint32_t>(na);
+    w->scan_ws = ar.take<char>(scan_ws_bytes(na));
+    w->units = ar.take<Unit>(p.max_units > 0 ? p.max_units : 1);
+    w->splits = ar.take<Split>(p.max_splits > 0 ? p.max_splits : 1);
+    w->partials = ar.take<float>((p.max_slots > 0 ? p.max_slots : 1) * (int64_t)p.tile_bins * 2);
+}
+
+template <typename KernelT>
+static int persistent_grid(KernelT kern, int requested, int* grid) {
+    if (requested > 0) {
+        *grid = requested;
+        return DDHF_OK;
+    }
+    int dev = 0, cus = 0, per_cu = 0;
+    DDHF_TRY_HIP(hipGetDevice(&dev));
+    DDHF_TRY_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+    DDHF_TRY_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, 64, 0));
+    *grid = cus * (per_cu > 0 ? per_cu : 1);
+    return DDHF_OK;
+}
+
+template <typename KernelPlain, typename KernelList, typename KernelQueue>
+static int run_plan(const Plan& p, const PlanWs& w, KernelPlain kp, KernelList kl, KernelQueue kq,
+                    const int32_t* row_ptr, const uint32_t* t_rel, const float* a,
+                    const int32_t* active, int32_t n_active, const GridDev& g, float* power,
+                    int grid_waves, hipStream_t s, const int32_t* n_dev) {
+    WorkDev wk{w.units, w.totals, w.counter, w.partials, n_dev};
+    if (n_dev && p.mode != kModePlain) return DDHF_EINVAL;
+    if (p.mode == kModePlain) {
+        const int64_t units = (int64_t)n_active * p.n_wtiles;
+        if (units > 0x7FFFFFFFLL) return DDHF_EINVAL;
+        hipLaunchKernelGGL(kp, dim3((unsigned)units), dim3(64), 0, s, row_ptr, t_rel, a, active,
+                           n_active, g, p.n_wtiles, power, wk);
+        DDHF_LAUNCH_CHECK();
+        return DDHF_OK;
+    }
+    const dim3 gb(blocks_for(n_active, 256));
+    hipLaunchKernelGGL(k_units_count, gb, dim3(256), 0, s, active, row_ptr, n_active, p.split,
+                       p.n_wtiles, w.c_units, w.c_slots, w.c_split);
     DDHF_LAUNCH_CHECK();
+    int rc = scan_exclusive_u32(w.c_units, w.o_units, n_active, w.scan_ws, s);
+    if (rc) return rc;
+    rc = scan_exclusive_u32(w.c_slots, w.o_slots, n_active, w.scan_ws, s);
+    if (rc) return rc;
+    rc = scan_exclusive_u32(w.c_split, w.o_split, n_active, w.scan_ws, s);
+    if (rc) return rc;
+    hipLaunchKernelGGL(k_units_fill, gb, dim3(256), 0, s, active, row_ptr, n_active, p.split,
+                       p.n_wtiles, w.c_units, w.c_slots, w.c_split, w.o_units, w.o_slots, w.o_split,
+                       w.units, w.splits, w.totals, w.counter);
+    DDHF_LAUNCH_CHECK();
+    if (p.mode == kModeList) {
+        if (p.max_units > 0x7FFFFFFFLL) return DDHF_EINVAL;
+        hipLaunchKernelGGL(kl, dim3((unsigned)p.max_units), dim3(64), 0, s, row_ptr, t_rel, a,
+                           active, n_active, g, p.n_wtiles, power, wk);
+    } else {
+        int grid = 0;
+        rc = persistent_grid(kq, grid_waves, &grid);
+        if (rc) return rc;
+        hipLaunchKernelGGL(kq, dim3((unsigned)grid), dim3(64), 0, s, row_ptr, t_rel, a, active,
+                           n_active, g, p.n_wtiles, power, wk);
+    }
+    DDHF_LAUNCH_CHECK();
+    if (p.split > 0 && p.max_splits > 0) {
+        const int64_t blocks = p.max_splits * p.n_wtiles;
+        if (blocks > 0x7FFFFFFFLL) return DDHF_EINVAL;
+        hipLaunchKernelGGL(k_combine, dim3((unsigned)blocks), dim3(256), 0, s, w.splits, w.totals,
+                           p.n_wtiles, p.tile_bins, (const float2*)w.partials, g.K, power);
+        DDHF_LAUNCH_CHECK();
+    }
     return DDHF_OK;
 }
 
@@ -152,28 +520,64 @@ extern "C" int ddhf_ndft_workspace_size(int32_t n_active, int64_t n_events,
                                         const ddhf_grid_t* grid, const ddhf_launch_t* launch,
                                         size_t* bytes) {
     if (!bytes || n_active < 0 || n_events < 0 || !grid_ok(grid)) return DDHF_EINVAL;
-    (void)launch;
-    *bytes = 256;
+    Plan p;
+    if (!make_plan(launch, n_active, n_events, grid->K, &p)) return DDHF_EINVAL;
+    Arena ar(nullptr, 0);
+    PlanWs w;
+    plan_layout(ar, p, n_active, &w);
+    *bytes = ar.used;
     return DDHF_OK;
 }
 
-extern "C" int ddhf_ndft_power(const int32_t* row_ptr, const uint32_t* t_rel, const float* a,
-                               const int32_t* active, int32_t n_active, const ddhf_grid_t* grid,
-                               float* power, const ddhf_launch_t* launch, void* ws,
-                               size_t ws_bytes, void* stream) {
-    if (!grid_ok(grid) || n_active < 0) return DDHF_EINVAL;
+#define DDHF_VALU_CASE(B)                                                                       \
+    case B:                                                                                     \
+        return run_plan(p, w, k_ndft_valu<B, kModePlain>, k_ndft_valu<B, kModeList>,            \
+                        k_ndft_valu<B, kModeQueue>, row_ptr, t_rel, a, active, n_active, g, power, \
+                        gw, s, n_dev);
+#define DDHF_MFMA_CASE(NB)                                                                      \
+    case NB:                                                                                    \
+        return run_plan(p, w, k_ndft_mfma<NB, kModePlain>, k_ndft_mfma<NB, kModeList>,          \
+                        k_ndft_mfma<NB, kModeQueue>, row_ptr, t_rel, a, active, n_active, g,    \
+                        power, gw, s, n_dev);
+
+namespace ddhf {
+int ndft_run(const int32_t* row_ptr, const uint32_t* t_rel, const float* a, const int32_t* active,
+             int32_t n_active, const int32_t* n_dev, int64_t n_events, const ddhf_grid_t* grid,
+             float* power, const ddhf_launch_t* launch, void* ws, size_t ws_bytes, hipStream_t s_) {
+    if (!grid_ok(grid) || n_active < 0 || n_events < 0) return DDHF_EINVAL;
     if (n_active == 0) return DDHF_OK;
     if (!row_ptr || !active || !power || !t_rel || !a) return DDHF_EINVAL;
-    (void)ws;
-    (void)ws_bytes;
+    Plan p;
+    if (!make_plan(launch, n_active, n_events, grid->K, &p)) return DDHF_EINVAL;
+    Arena ar(ws, ws_bytes);
+    PlanWs w;
+    plan_layout(ar, p, n_active, &w);
+    if (!ws || !ar.fits()) return DDHF_ENOSPACE;
     const GridDev g = grid_dev(grid);
-    hipStream_t s = as_stream(stream);
-    int bpl = launch ? launch->bins_per_lane : 32;
-    switch (bpl) {
-        case 8: return launch_valu<8>(row_ptr, t_rel, a, active, n_active, g, power, s);
-        case 16: return launch_valu<16>(row_ptr, t_rel, a, active, n_active, g, power, s);
-        case 32: return launch_valu<32>(row_ptr, t_rel, a, active, n_active, g, power, s);
-        case 64: return launch_valu<64>(row_ptr, t_rel, a, active, n_active, g, power, s);
+    hipStream_t s = s_;
+    const int gw = launch ? launch->grid_waves : 0;
+    if (p.kernel == DDHF_KERNEL_MFMA) {
+        switch (p.nb) {
+            DDHF_MFMA_CASE(1)
+            DDHF_MFMA_CASE(2)
+            DDHF_MFMA_CASE(4)
+            default: return DDHF_EINVAL;
+        }
+    }
+    switch (p.bpl) {
+        DDHF_VALU_CASE(8)
+        DDHF_VALU_CASE(16)
+        DDHF_VALU_CASE(32)
+        DDHF_VALU_CASE(64)
         default: return DDHF_EINVAL;
     }
+}
+}  // namespace ddhf
+
+extern "C" int ddhf_ndft_power(const int32_t* row_ptr, const uint32_t* t_rel, const float* a,
+                               const int32_t* active, int32_t n_active, int64_t n_events,
+                               const ddhf_grid_t* grid, float* power, const ddhf_launch_t* launch,
+                               void* ws, size_t ws_bytes, void* stream) {
+    return ndft_run(row_ptr, t_rel, a, active, n_active, nullptr, n_events, grid, power, launch, ws,
+                    ws_bytes, as_stream(stream));
 }

@@ -153,10 +153,10 @@ def ddhf_ndft_workspace_size(n_active, n_events, grid: Grid, launch: Optional[La
     return b.value
 
 
-def ddhf_ndft_power(row_ptr, t_rel, a, active, n_active, grid: Grid, power,
+def ddhf_ndft_power(row_ptr, t_rel, a, active, n_active, n_events, grid: Grid, power,
                     launch: Optional[Launch] = None, ws=None, stream=None):
     rc = lib().ddhf_ndft_power(_p(row_ptr), _p(t_rel), _p(a), _p(active), C.c_int32(n_active),
-                               C.byref(grid), _p(power),
+                               C.c_int64(n_events), C.byref(grid), _p(power),
                                C.byref(launch) if launch is not None else None, _p(ws),
                                C.c_size_t(ws.numel() if ws is not None else 0), _stream(stream))
     _check(rc, "ddhf_ndft_power")
@@ -281,8 +281,8 @@ class Window:
                                                               self.launch), self.dev)
 
     def spectra(self, stream=None):
-        ddhf_ndft_power(self.row_ptr, self.t_rel, self.a, self.active, self.n_active, self.grid,
-                        self.power, self.launch, self.ws_ndft, stream)
+        ddhf_ndft_power(self.row_ptr, self.t_rel, self.a, self.active, self.n_active, self.n,
+                        self.grid, self.power, self.launch, self.ws_ndft, stream)
 
     def score(self, stream=None, snr_all=None):
         ddhf_comb_score(self.power, self.n_active, self.grid, self.prm, self.sf, self.snr,

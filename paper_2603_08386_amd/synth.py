@@ -330,7 +330,8 @@ class EventStream:
 
     def __init__(self, seed: int = 5, W: int = 1280, H: int = 720,
                  rate_hz: float = 10e6, packet_us: int = 100,
-                 drone_burst: int = 4, t_origin: int = T0_US):
+                 drone_burst: int = 4, t_origin: int = T0_US, clutter_frac: float = 0.15,
+                 noise_hz: float = 2.0):
         self.rng = np.random.Generator(np.random.PCG64(seed))
         self.W, self.H = W, H
         self.packet_us = packet_us
@@ -338,7 +339,8 @@ class EventStream:
         self.t_us = 0
         self.drone_burst = drone_burst
         self.rotors = []
-        for (dx, dy) in [(300, 200), (700, 450), (1050, 250)]:
+        centres = [(int(W * fx), int(H * fy)) for fx, fy in [(0.234, 0.278), (0.547, 0.625), (0.820, 0.347)]]
+        for (dx, dy) in centres:
             for (ox, oy) in [(-8, -8), (8, -8), (-8, 8), (8, 8)]:
                 self.rotors.append((dx + ox, dy + oy, 5, self.rng.uniform(150.0, 400.0) / 2.0,
                                     np.random.Generator(np.random.PCG64(self.rng.integers(1 << 62)))))
@@ -355,10 +357,10 @@ class EventStream:
             self._rotor_cache.append((px, py, period, phi, tau))
         drone_rate = sum(px.size * 2 * (1e6 / per) * drone_burst
                          for (px, _, per, _, _) in self._rotor_cache)
-        self.noise_rate_px = 2.0
+        self.noise_rate_px = noise_hz
         self.clutter_rate = max(rate_hz - drone_rate - self.noise_rate_px * W * H, 0.0)
         field = _smooth_field(self.rng, H + 64, W + 64)
-        self.clutter_map = field >= np.quantile(field, 0.85)
+        self.clutter_map = field >= np.quantile(field, 1.0 - clutter_frac)
         self.clutter_pix = np.flatnonzero(self.clutter_map.ravel())
         self.offset = np.zeros(2)
         self.label = np.zeros((H, W), bool)

@@ -61,5 +61,5 @@ def test_host_side_validation_needs_no_gpu(lib):
     good = Grid(1000, 1000, 1024, 0, 20000)
     assert lib.ddhf_ndft_workspace_size(1, C.c_int64(1), C.byref(good), None, C.byref(b)) == 0
     # zero active pixels is a no-op that needs no pointers
-    assert lib.ddhf_ndft_power(None, None, None, None, 0, C.byref(good), None, None, None,
-                               C.c_size_t(0), None) == 0
+    assert lib.ddhf_ndft_power(None, None, None, None, 0, C.c_int64(0), C.byref(good), None, None,
+                               None, C.c_size_t(0), None) == 0

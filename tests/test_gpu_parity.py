@@ -99,11 +99,15 @@ def gpu_power(win, launch=None, params=None):
     return g, to_np(g.power, g.n_active * K).reshape(g.n_active, K)
 
 
-@pytest.mark.parametrize("bpl", [8, 16, 32, 64])
-def test_ndft_tiny_full(bpl):
+LAUNCHES = [(D.DDHF_KERNEL_VALU, b) for b in (8, 16, 32, 64)] + \
+           [(D.DDHF_KERNEL_MFMA, b) for b in (16, 32, 64)]
+
+
+@pytest.mark.parametrize("kernel,bpl", LAUNCHES)
+def test_ndft_tiny_full(kernel, bpl):
     win = synth.tiny_window(1)
-    banner(f"ndft tiny bpl={bpl}")
-    g, P = gpu_power(win, D.make_launch(D.DDHF_KERNEL_VALU, bpl))
+    banner(f"ndft tiny kernel={kernel} bpl={bpl}")
+    g, P = gpu_power(win, D.make_launch(kernel, bpl))
     r = oracle_window(win)
     assert np.array_equal(to_np(g.active, g.n_active), r["active"])
     P64 = oracle.ndft_power(r["row_ptr"], r["t_rel"], r["a"], r["active"], win.grid)
@@ -112,13 +116,14 @@ def test_ndft_tiny_full(bpl):
     assert err <= TOL_P
 
 
-def test_ndft_mode_grid_and_ragged_bins():
+@pytest.mark.parametrize("kernel,bpl", [(0, 32), (1, 64), (1, 16)])
+def test_ndft_mode_grid_and_ragged_bins(kernel, bpl):
     """Mode grid (integer modes over the window) with K not a multiple of
     any tile, T_w = 33,333 us (30 FPS windows)."""
     grid = Grid(f0=0, df=1, K=1000, mode=1, T_w_us=33_333)
     win = synth.random_window(21, 40, 30, 33_333, 30_000, grid, params=Params(n_min=2))
-    banner("ndft mode grid")
-    g, P = gpu_power(win)
+    banner(f"ndft mode grid kernel={kernel}")
+    g, P = gpu_power(win, D.make_launch(kernel, bpl))
     r = oracle_window(win)
     P64 = oracle.ndft_power(r["row_ptr"], r["t_rel"], r["a"], r["active"], grid)
     assert power_err(P, P64, r["row_ptr"], r["active"], r["a"]) <= TOL_P
@@ -145,10 +150,11 @@ def test_ndft_closed_forms_on_gpu():
         assert P[1][250 * n - 1] == pytest.approx(100.0, rel=1e-4)
 
 
-def test_ndft_medium_sampled():
+@pytest.mark.parametrize("kernel,bpl", [(0, 32), (1, 64), (1, 32)])
+def test_ndft_medium_sampled(kernel, bpl):
     win = synth.medium_window(2)
-    banner(f"ndft medium n={win.n}")
-    g, P = gpu_power(win)
+    banner(f"ndft medium n={win.n} kernel={kernel} bpl={bpl}")
+    g, P = gpu_power(win, D.make_launch(kernel, bpl))
     r = oracle_window(win)
     assert np.array_equal(to_np(g.active, g.n_active), r["active"])
     rp = r["row_ptr"]
@@ -160,10 +166,11 @@ def test_ndft_medium_sampled():
     assert err <= TOL_P
 
 
-def test_ndft_deterministic():
+@pytest.mark.parametrize("kernel,bpl", [(0, 32), (1, 64)])
+def test_ndft_deterministic(kernel, bpl):
     win = synth.tiny_window(3)
-    _, P1 = gpu_power(win)
-    _, P2 = gpu_power(win)
+    _, P1 = gpu_power(win, D.make_launch(kernel, bpl))
+    _, P2 = gpu_power(win, D.make_launch(kernel, bpl))
     assert np.array_equal(P1, P2)
 
 
@@ -224,7 +231,10 @@ def test_comb_random_spectra_many_shapes():
     rng = np.random.default_rng(5)
     for K, M, dk, hmin, f0, df in [(1024, 5, 3, 3, 1000, 1000), (3981, 4, 3, 4, 10_000, 500),
                                    (3991, 4, 3, 4, 10_000, 1000), (777, 6, 2, 2, 750, 500),
-                                   (129, 3, 0, 2, 0, 1), (300, 16, 4, 8, 10_000, 500)]:
+                                   (129, 3, 0, 2, 0, 1), (300, 16, 4, 8, 10_000, 500),
+                                   (5000, 4, 3, 4, 10_000, 1000),      # general kernel: K > 4095
+                                   (2000, 32, 8, 4, 10_000, 500),      # general kernel: wide band
+                                   (600, 4, 6, 3, 10_000, 500)]:       # runtime window width
         grid = Grid(f0=f0, df=df, K=K)
         prm = Params(M=M, dk=dk, h_min=hmin)
         P = rng.exponential(size=(6, K)).astype(np.float32)
@@ -352,3 +362,77 @@ def test_end_to_end_tiny():
                [(q["x0"], q["y0"], q["x1"], q["y1"], q["n_px"]) for q in boxes64]
     # the single synthetic drone is found
     assert n >= 1
+
+
+# ---------------------------------------------------------------------------
+# 6. persistent / split launches
+# ---------------------------------------------------------------------------
+
+FORMS = [
+    # kernel, bpl, split, persistent, order_by_cost
+    (0, 32, 0, 1, False),
+    (0, 16, 64, 0, True),
+    (0, 32, 100, 1, True),
+    (1, 64, 0, 1, False),
+    (1, 64, 128, 1, True),
+    (1, 32, 50, 0, False),
+    (1, 16, 300, 1, True),
+]
+
+
+def gpu_power_form(win, kernel, bpl, split, persistent, cost, grid_waves=0):
+    launch = D.make_launch(kernel, bpl, split_events=split, persistent=persistent,
+                           grid_waves=grid_waves)
+    g = D.Window(win.x, win.y, win.p, win.t, win.W, win.H, win.t0, win.T_w, win.grid, win.params,
+                 device=DEV, launch=launch, order_by_cost=cost)
+    g.index()
+    g.fetch_n_active()
+    g.alloc_spectra()
+    g.spectra()
+    torch.cuda.synchronize()
+    K = win.grid.K
+    return g, to_np(g.power, g.n_active * K).reshape(g.n_active, K), to_np(g.active, g.n_active)
+
+
+@pytest.mark.parametrize("form", FORMS)
+def test_ndft_launch_forms_tiny(form):
+    win = synth.tiny_window(1)
+    banner(f"ndft forms tiny {form}")
+    g, P, act = gpu_power_form(win, *form)
+    r = oracle_window(win)
+    order = np.argsort(act)
+    assert np.array_equal(act[order], r["active"])
+    P64 = oracle.ndft_power(r["row_ptr"], r["t_rel"], r["a"], r["active"], win.grid)
+    assert power_err(P[order], P64, r["row_ptr"], r["active"], r["a"]) <= TOL_P
+    # deterministic for a given launch
+    _, P2, _ = gpu_power_form(win, *form)
+    assert np.array_equal(P, P2)
+
+
+def test_ndft_persistent_matches_plain_bit_exact():
+    win = synth.tiny_window(2)
+    for kernel, bpl in [(0, 32), (1, 64)]:
+        _, Pa, _ = gpu_power_form(win, kernel, bpl, 0, 0, False)
+        _, Pb, _ = gpu_power_form(win, kernel, bpl, 0, 1, False)
+        _, Pc, _ = gpu_power_form(win, kernel, bpl, 0, 1, False, grid_waves=7)
+        assert np.array_equal(Pa, Pb) and np.array_equal(Pa, Pc)
+
+
+@pytest.mark.parametrize("form", [(1, 64, 512, 1, True), (0, 32, 0, 0, False)])
+def test_ndft_large_sampled(form):
+    """1280x720, 100 ms, ~11 M events with 5000-event pixels: sampled rows
+    (count deciles + every pixel at the maximum count) against the oracle."""
+    win = synth.large_window(3)
+    banner(f"ndft large n={win.n} form={form}")
+    g, P, act = gpu_power_form(win, *form)
+    r = oracle_window(win)
+    order = np.argsort(act, kind="stable")
+    assert np.array_equal(act[order], r["active"])
+    rp = r["row_ptr"]
+    counts = rp[r["active"] + 1] - rp[r["active"]]
+    rows = stratified_sample(counts, 40, np.random.default_rng(1))
+    assert counts[rows].max() == 5000
+    P64 = oracle.ndft_power(rp, r["t_rel"], r["a"], r["active"][rows], win.grid)
+    err = power_err(P[order][rows], P64, rp, r["active"][rows], r["a"])
+    banner(f"  sampled rows {rows.size} max err {err:.3e}")
+    assert err <= TOL_P
