@@ -1,9 +1,19 @@
 """Benchmark of the DDHF hot path on one MI355X.
 
-A step is one pass of the whole path over one resident window of events:
-pixel CSR build, active list, per-pixel NDFT power, spectral flatness and
-comb score, mask / components / boxes, and the box count back on the host.
-Prints one JSON line (see the design doc for the fields).
+Window leg (the step): one pass of the whole path over one resident
+1280x720, 100 ms window of about 11 M events -- pixel CSR build, active list,
+per-pixel NDFT power, spectral flatness and comb score, mask / components /
+boxes, and the box count back on the host.  `value` is active pixels x bins
+per second of the whole step; the `ndft` block and `roofline` are for the NDFT
+kernel alone (HIP events on its launch stream).
+
+Stream leg: a continuous 1280x720 stream at about 10 M events/s in 100 us
+packets, 50 ms sliding window advanced every 1 ms; frame latency is measured
+on the host from the push of a step's last packet to its boxes being readable,
+for the graph-replayed streaming step and for a plain recompute of the window
+(events copied to the device, whole path, boxes back).
+
+Prints one JSON line.
 """
 from __future__ import annotations
 
@@ -37,12 +47,14 @@ def parse():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="large_1280x720", choices=sorted(WORKLOADS))
     ap.add_argument("--kernel", default="auto", choices=["auto", "valu", "mfma"])
-    ap.add_argument("--bpl", type=int, default=32)
+    ap.add_argument("--bpl", type=int, default=64)
     ap.add_argument("--split", type=int, default=0, help="split pixels with more events")
     ap.add_argument("--persistent", type=int, default=0)
-    ap.add_argument("--cost-order", type=int, default=0)
+    ap.add_argument("--cost-order", type=int, default=1)
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
                     help="target CPU time of the oracle baseline sample (0 = skip)")
+    ap.add_argument("--stream-steps", type=int, default=400, help="timed stream steps (0 = skip)")
+    ap.add_argument("--plain-frames", type=int, default=15, help="plain recompute frames timed")
     return ap.parse_args()
 
 
@@ -55,8 +67,8 @@ def kernel_source_digest(names):
 
 
 def load_traffic(kernel_tag, digest):
-    """HBM bytes per launch measured with rocprofv3 --pmc (FETCH_SIZE, WRITE_SIZE),
-    valid only while the kernel source is unchanged."""
+    """HBM bytes per launch from rocprofv3 --pmc (FETCH_SIZE, WRITE_SIZE), scaled by
+    a copy-kernel calibration; valid only while the kernel source is unchanged."""
     path = os.path.join(ROOT, "profiles", f"traffic_{kernel_tag}.json")
     if not os.path.exists(path):
         return None
@@ -90,6 +102,81 @@ def cpu_baseline(win, target_s):
                        f"(NDFT power + flatness + comb, FP64, one thread), {spent:.1f} s")
 
 
+def stream_leg(args, D, synth, launch):
+    """p50/p99 frame latency of the streaming step and of a plain recompute."""
+    import torch
+    from paper_2603_08386_amd.stream import Stream
+
+    W, H, T_w, step_us, pkt_us = 1280, 720, 50_000, 1000, 100
+    grid = synth.Grid(f0=10_000, df=1000, K=3991)
+    prm = synth.Params(M=4, dk=3, h_min=4, n_min=6, tau_sf=0.89, tau_comb=1.5, a_min=49, alpha=3.0)
+    gen = synth.EventStream(seed=5, W=W, H=H, rate_hz=10e6, packet_us=pkt_us)
+    per_step = step_us // pkt_us
+    warm = T_w // step_us + 10
+    n_steps = warm + args.stream_steps
+    packets = [gen.next_packet() for _ in range(n_steps * per_step)]
+    st = Stream(W, H, T_w, gen.t_origin, grid, prm,
+                launch=D.make_launch(launch.kernel, launch.bins_per_lane),
+                ring_cap=64, max_step_events=32768, max_touched=32768, max_boxes=256)
+    lat, boxes_seen = [], 0
+    t_loop0 = None
+    for s in range(n_steps):
+        if s == warm:
+            t_loop0 = time.perf_counter()
+        pk = packets[s * per_step:(s + 1) * per_step]
+        for q in pk[:-1]:
+            st.push(*q)
+        t_a = time.perf_counter()
+        st.push(*pk[-1])
+        boxes, nb = st.step(gen.t_origin + (s + 1) * step_us, use_graph=True)
+        t_b = time.perf_counter()
+        if s >= warm:
+            lat.append((t_b - t_a) * 1e3)
+            boxes_seen = nb
+    t_loop = time.perf_counter() - t_loop0
+    stats = st.stats()
+    n_ev = sum(int(q[3].size) for q in packets[warm * per_step:])
+    st.close()
+
+    # plain recompute of the same sliding window, every few steps
+    x = np.concatenate([q[0] for q in packets]); y = np.concatenate([q[1] for q in packets])
+    p = np.concatenate([q[2] for q in packets]); t = np.concatenate([q[3] for q in packets])
+    frames = np.linspace(warm, n_steps - 1, max(args.plain_frames, 2)).astype(int)
+    cap = 0
+    for s in frames:
+        t_now = gen.t_origin + (s + 1) * step_us
+        cap = max(cap, int(np.sum((t >= t_now - T_w) & (t < t_now))))
+    g = None
+    plain = []
+    for s in frames:
+        t_now = gen.t_origin + (s + 1) * step_us
+        sel = (t >= t_now - T_w) & (t < t_now)
+        xs, ys, ps, ts = x[sel], y[sel], p[sel], t[sel]
+        if g is None:
+            g = D.Window(xs, ys, ps, ts, W, H, t_now - T_w, T_w, grid, prm, device="cuda:0",
+                         launch=launch, capacity=cap)
+            g.run()
+        torch.cuda.synchronize()
+        t_a = time.perf_counter()
+        g.reload(xs, ys, ps, ts, t_now - T_w)
+        g.run()
+        t_b = time.perf_counter()
+        plain.append((t_b - t_a) * 1e3)
+    return {
+        "workload": "stream_1280x720_10Mevps", "window_ms": T_w / 1000, "step_ms": step_us / 1000,
+        "packet_us": pkt_us, "steps_timed": args.stream_steps,
+        "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
+        "mean_ms": float(np.mean(lat)),
+        "steps_per_s": args.stream_steps / t_loop, "events_per_s": n_ev / t_loop,
+        "active_pixels_last": stats["n_active"], "recomputed_last": stats["n_recomputed"],
+        "ring_overflow": stats["ring_overflow"], "touched_overflow": stats["touched_overflow"],
+        "boxes_last": boxes_seen,
+        "plain_recompute": {"frames": len(plain), "p50_ms": float(np.percentile(plain, 50)),
+                            "p99_ms": float(np.percentile(plain, 99)),
+                            "events_per_window": cap},
+    }
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -106,25 +193,41 @@ def main():
     print(f"[bench] workload {args.workload}: {win.n} events, generated in "
           f"{time.time() - t_gen:.1f}s", file=sys.stderr, flush=True)
 
-    kernel = D.DDHF_KERNEL_VALU if args.kernel in ("auto", "valu") else D.DDHF_KERNEL_MFMA
-    launch = D.make_launch(kernel, args.bpl, split_events=args.split, persistent=args.persistent)
-    g = D.window_from_synth(win, device="cuda:0", launch=launch, order_by_cost=bool(args.cost_order))
+    if args.kernel == "auto":
+        launch = None
+    else:
+        kernel = D.DDHF_KERNEL_VALU if args.kernel == "valu" else D.DDHF_KERNEL_MFMA
+        launch = D.make_launch(kernel, args.bpl, split_events=args.split,
+                               persistent=args.persistent)
+    g = D.window_from_synth(win, device="cuda:0", launch=launch,
+                            order_by_cost=bool(args.cost_order))
     stream = torch.cuda.current_stream()
     K = int(win.grid.K)
+    tune = None
+    if launch is None:
+        g.index()
+        g.fetch_n_active()
+        g.alloc_spectra()
+        t0 = time.perf_counter()
+        launch, best_ms = g.autotune()
+        tune = {"launch": [launch.kernel, launch.bins_per_lane, launch.split_events,
+                           launch.persistent], "best_ms": best_ms,
+                "seconds": time.perf_counter() - t0}
+        print(f"[bench] autotuned launch {tune}", file=sys.stderr, flush=True)
 
     ev = lambda: torch.cuda.Event(enable_timing=True)
     stage_ms = {"index": [], "ndft": [], "comb": [], "detect": []}
     frame_ms = []
 
     def step(record):
-        e0, e1, e2, e3, e4 = ev(), ev(), ev(), ev(), ev()
+        e0, e1, e1b, e2, e3, e4 = ev(), ev(), ev(), ev(), ev(), ev()
         t_a = time.perf_counter()
         e0.record(stream)
         g.index()
         e1.record(stream)
         na = g.fetch_n_active()
         g.alloc_spectra()
-        e1b = ev(); e1b.record(stream)
+        e1b.record(stream)
         g.spectra()
         e2.record(stream)
         g.score()
@@ -158,7 +261,7 @@ def main():
     ndft_ms = float(np.mean(stage_ms["ndft"]))
     flops = FLOP_PER_EVENT_BIN * ev_bins
     achieved_tflops = flops / (ndft_ms * 1e-3) / 1e12
-    tag = "ndft_valu" if kernel == D.DDHF_KERNEL_VALU else "ndft_mfma"
+    tag = "ndft_valu" if launch.kernel == D.DDHF_KERNEL_VALU else "ndft_mfma"
     digest = kernel_source_digest(["ndft.hip", "ddhf_internal.h"])
     traffic = load_traffic(f"{tag}_{args.workload}", digest)
 
@@ -178,22 +281,29 @@ def main():
         "config": {"workload": args.workload, "sensor": [win.W, win.H], "T_w_us": win.T_w,
                    "events": win.n, "active_pixels": int(na), "events_in_active": events_active,
                    "K": K, "grid_mHz": [int(win.grid.f0), int(win.grid.df)],
-                   "ndft_kernel": tag, "bins_per_lane": args.bpl, "split_events": args.split,
-                   "persistent": args.persistent, "cost_order": args.cost_order},
+                   "ndft_kernel": tag, "bins_per_lane": launch.bins_per_lane,
+                   "split_events": launch.split_events, "persistent": launch.persistent,
+                   "cost_order": args.cost_order, "autotune": tune},
         "ndft": {"ms": ndft_ms, "pixel_bins_per_s": na * K / (ndft_ms * 1e-3),
                  "event_bins_per_s": ev_bins / (ndft_ms * 1e-3),
                  "pct_fp32_peak": 100.0 * achieved_tflops / FP32_PEAK_TFLOPS},
         "stages_ms": {k: float(np.mean(v)) for k, v in stage_ms.items()},
         "frame_latency_ms": {"p50": float(np.percentile(frame_ms, 50)),
                              "p99": float(np.percentile(frame_ms, 99)),
-                             "path": "plain recompute of one 100 ms window per frame"},
+                             "path": "whole 100 ms window recomputed per frame, inputs resident"},
         "boxes": nbox,
-        "roofline": {"bound": "alu" if kernel == D.DDHF_KERNEL_VALU else "mfma",
+        "roofline": {"bound": "alu" if launch.kernel == D.DDHF_KERNEL_VALU else "mfma",
                      "kernel": tag, "achieved": achieved_tflops, "peak": FP32_PEAK_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved_tflops / FP32_PEAK_TFLOPS,
                      "traffic": traffic},
     }
+    if args.stream_steps > 0:
+        print("[bench] stream leg", file=sys.stderr, flush=True)
+        out["stream"] = stream_leg(args, D, synth, launch)
+        out["frame_latency_ms"]["stream_p50"] = out["stream"]["p50_ms"]
+        out["frame_latency_ms"]["stream_p99"] = out["stream"]["p99_ms"]
     if args.cpu_seconds > 0:
+        print("[bench] cpu baseline", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(win, args.cpu_seconds)
     print(json.dumps(out), flush=True)
 

@@ -186,6 +186,24 @@ int ddhf_ndft_power(const int32_t* row_ptr, const uint32_t* t_rel, const float* 
                     const ddhf_grid_t* grid, float* power, const ddhf_launch_t* launch, void* ws,
                     size_t ws_bytes, void* stream);
 
+/* ---- 3b. launch autotuner ------------------------------------------------ */
+
+int ddhf_autotune_workspace_size(int32_t n_active, int64_t n_events, const ddhf_grid_t* grid,
+                                 size_t* bytes);
+
+/* Picks the fastest NDFT launch shape (kernel, tile, split threshold,
+ * persistent) for this CSR by timing a fixed candidate list with HIP events
+ * on `stream` (it runs ddhf_ndft_power several times and synchronises).
+ * power [n_active * K] receives a valid spectrum as a side effect.  With a
+ * cache_path (nullable), results are read from / appended to that JSON-lines
+ * file under a key of device architecture, grid, and the active-pixel and
+ * event counts rounded to powers of two; a cache hit returns without timing
+ * (*best_ms = -1).  ws must hold ddhf_autotune_workspace_size bytes. */
+int ddhf_autotune(const int32_t* row_ptr, const uint32_t* t_rel, const float* a,
+                  const int32_t* active, int32_t n_active, int64_t n_events,
+                  const ddhf_grid_t* grid, float* power, void* ws, size_t ws_bytes,
+                  const char* cache_path, ddhf_launch_t* out, float* best_ms, void* stream);
+
 /* ---- 4. spectral flatness + harmonic comb (Eq. 7-11) --------------------- */
 
 /* For each row u of power [n_active * K]:

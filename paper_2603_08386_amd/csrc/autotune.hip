@@ -1,0 +1,156 @@
+// Autotuner for the NDFT launch shape.
+//
+// Times a fixed list of candidate launches (kernel, tile, split threshold,
+// persistent or not) on the caller's own CSR with HIP events, and returns the
+// fastest.  Results are cached in a JSON-lines file keyed by the device
+// architecture, the grid, and a coarse signature of the event-count
+// distribution (active pixels and events, each rounded to a power of two), so
+// a later call on a similar window reads the cache instead of timing.
+#include "ddhf_internal.h"
+
+#include <stdio.h>
+#include <string.h>
+
+#include <string>
+
+namespace ddhf {
+
+static const ddhf_launch_t kCandidates[] = {
+    // kernel, bins_per_lane, split_events, persistent, grid_waves, reserved
+    {DDHF_KERNEL_MFMA, 64, 0, 0, 0, 0},    {DDHF_KERNEL_MFMA, 32, 0, 0, 0, 0},
+    {DDHF_KERNEL_MFMA, 16, 0, 0, 0, 0},    {DDHF_KERNEL_MFMA, 64, 0, 1, 0, 0},
+    {DDHF_KERNEL_MFMA, 64, 512, 1, 0, 0},  {DDHF_KERNEL_MFMA, 64, 2048, 1, 0, 0},
+    {DDHF_KERNEL_MFMA, 64, 512, 0, 0, 0},  {DDHF_KERNEL_MFMA, 32, 1024, 1, 0, 0},
+    {DDHF_KERNEL_VALU, 32, 0, 0, 0, 0},    {DDHF_KERNEL_VALU, 64, 0, 0, 0, 0},
+    {DDHF_KERNEL_VALU, 32, 256, 1, 0, 0},
+};
+static const int kNumCandidates = (int)(sizeof(kCandidates) / sizeof(kCandidates[0]));
+
+static int ceil_log2(int64_t v) {
+    int b = 0;
+    while (((int64_t)1 << b) < v) ++b;
+    return b;
+}
+
+static std::string cache_key(const ddhf_grid_t* g, int32_t n_active, int64_t n_events) {
+    int dev = 0;
+    hipDeviceProp_t prop;
+    std::string arch = "unknown";
+    if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess)
+        arch = prop.gcnArchName;
+    const size_t colon = arch.find(':');
+    if (colon != std::string::npos) arch = arch.substr(0, colon);
+    char buf[256];
+    snprintf(buf, sizeof(buf), "%s|K%d|m%d|f0_%lld|df_%lld|act2^%d|ev2^%d", arch.c_str(), g->K,
+             g->mode, (long long)g->f0, (long long)g->df, ceil_log2(n_active),
+             ceil_log2(n_events));
+    return buf;
+}
+
+static bool cache_lookup(const char* path, const std::string& key, ddhf_launch_t* out) {
+    if (!path) return false;
+    FILE* f = fopen(path, "r");
+    if (!f) return false;
+    char line[1024];
+    bool found = false;
+    const std::string needle = "\"key\": \"" + key + "\"";
+    while (fgets(line, sizeof(line), f)) {
+        if (!strstr(line, needle.c_str())) continue;
+        int k = 0, b = 0, sp = 0, pe = 0, gw = 0;
+        const char* p = strstr(line, "\"launch\": [");
+        if (p && sscanf(p, "\"launch\": [%d, %d, %d, %d, %d]", &k, &b, &sp, &pe, &gw) == 5) {
+            out->kernel = k;
+            out->bins_per_lane = b;
+            out->split_events = sp;
+            out->persistent = pe;
+            out->grid_waves = gw;
+            out->reserved = 0;
+            found = true;  // the last matching line wins
+        }
+    }
+    fclose(f);
+    return found;
+}
+
+static void cache_store(const char* path, const std::string& key, const ddhf_launch_t& l, float ms) {
+    if (!path) return;
+    FILE* f = fopen(path, "a");
+    if (!f) return;
+    fprintf(f, "{\"key\": \"%s\", \"launch\": [%d, %d, %d, %d, %d], \"ms\": %.4f}\n", key.c_str(),
+            l.kernel, l.bins_per_lane, l.split_events, l.persistent, l.grid_waves, ms);
+    fclose(f);
+}
+
+}  // namespace ddhf
+
+using namespace ddhf;
+
+extern "C" int ddhf_autotune_workspace_size(int32_t n_active, int64_t n_events,
+                                            const ddhf_grid_t* grid, size_t* bytes) {
+    if (!bytes) return DDHF_EINVAL;
+    size_t mx = 0;
+    for (int i = 0; i < kNumCandidates; ++i) {
+        size_t b = 0;
+        const int rc = ddhf_ndft_workspace_size(n_active, n_events, grid, &kCandidates[i], &b);
+        if (rc) return rc;
+        if (b > mx) mx = b;
+    }
+    *bytes = mx;
+    return DDHF_OK;
+}
+
+extern "C" int ddhf_autotune(const int32_t* row_ptr, const uint32_t* t_rel, const float* a,
+                             const int32_t* active, int32_t n_active, int64_t n_events,
+                             const ddhf_grid_t* grid, float* power, void* ws, size_t ws_bytes,
+                             const char* cache_path, ddhf_launch_t* out, float* best_ms,
+                             void* stream) {
+    if (!out || !grid || n_active < 0 || n_events < 0) return DDHF_EINVAL;
+    const std::string key = cache_key(grid, n_active, n_events);
+    if (cache_lookup(cache_path, key, out)) {
+        if (best_ms) *best_ms = -1.0f;
+        return DDHF_OK;
+    }
+    hipStream_t s = as_stream(stream);
+    hipEvent_t e0, e1;
+    DDHF_TRY_HIP(hipEventCreate(&e0));
+    DDHF_TRY_HIP(hipEventCreate(&e1));
+    float best = 3.0e38f;
+    int best_i = -1;
+    int rc = DDHF_OK;
+    for (int i = 0; i < kNumCandidates && n_active > 0; ++i) {
+        const ddhf_launch_t* L = &kCandidates[i];
+        size_t need = 0;
+        if (ddhf_ndft_workspace_size(n_active, n_events, grid, L, &need) != DDHF_OK ||
+            need > ws_bytes)
+            continue;
+        rc = ndft_run(row_ptr, t_rel, a, active, n_active, nullptr, n_events, grid, power, L, ws,
+                      ws_bytes, s);  // warm-up
+        if (rc) break;
+        float t_min = 3.0e38f;
+        for (int rep = 0; rep < 3; ++rep) {
+            if (hipEventRecord(e0, s) != hipSuccess) { rc = DDHF_EHIP; break; }
+            rc = ndft_run(row_ptr, t_rel, a, active, n_active, nullptr, n_events, grid, power, L,
+                          ws, ws_bytes, s);
+            if (rc) break;
+            if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) {
+                rc = DDHF_EHIP;
+                break;
+            }
+            float ms = 0.0f;
+            if (hipEventElapsedTime(&ms, e0, e1) != hipSuccess) { rc = DDHF_EHIP; break; }
+            if (ms < t_min) t_min = ms;
+        }
+        if (rc) break;
+        if (t_min < best) {
+            best = t_min;
+            best_i = i;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (rc) return rc;
+    *out = best_i >= 0 ? kCandidates[best_i] : kCandidates[0];
+    if (best_ms) *best_ms = best_i >= 0 ? best : -1.0f;
+    if (best_i >= 0) cache_store(cache_path, key, *out, best);
+    return DDHF_OK;
+}

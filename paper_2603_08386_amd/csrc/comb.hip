@@ -329,41 +329,54 @@ __global__ __launch_bounds__(kCombThreads) void k_comb(const float* __restrict__
 }
 
 // ---------------------------------------------------------------------------
-// Fast path (K <= 4095, band <= 254): the row stays in registers across
-// phases, the band is found by a three-level 8-bit radix select (exponent,
-// then 8 + 8 mantissa bits; the 24-bit prefix orders the values), and one u32
-// per bin packs the exclusive prefix counts of below-band bins (bits 0-11) and
-// in-band bins (bits 12-19) with the bin's own band index (bits 24-31, 0xFF if
-// outside the band).
+// Fast path (K <= 4095, band <= 254).  The row is held in registers across
+// phases.  The band of ranks is found by a two-level radix select on the top
+// 22 bits of the FP32 bit patterns (11 + 11 bits, 2048-bucket histograms);
+// the few values sharing the band's 22-bit keys are ranked exactly by
+// (value, bin).  The spectrum array is then overwritten in place by the
+// window maxima max(P[k - dk .. k + dk]), and one u32 per bin packs the
+// exclusive prefix counts of below-band bins (bits 0-11) and in-band bins
+// (bits 12-19) with the bin's own band index (bits 24-31, 0xFF outside).  A
+// candidate reads three words per harmonic window; window bins inside the
+// band are gathered into registers and the complement median's rank is fixed
+// there.
 // ---------------------------------------------------------------------------
 constexpr int kFastItems = 16;    // bins per thread: K <= 4096
 constexpr int kListCap = 1024;
+constexpr int kInbCap = 8;        // in-band window bins kept in registers per candidate
 
 struct Loc {
     int d;
     uint32_t before;
 };
 
-// Locate, in a 256-bucket histogram (one bucket per thread) offset by `base`,
-// the bucket holding rank tgt; returns it in *out (only one thread writes).
-__device__ __forceinline__ void locate256(const uint32_t* h, uint32_t base, int32_t tgt, Loc* out,
-                                          uint32_t* scr) {
+// 2048-bucket histogram, 8 buckets per thread: the bucket holding rank tgt
+// (counting `base` elements before the histogram); only one thread writes.
+__device__ __forceinline__ void locate2048(const uint32_t* h, uint32_t base, int32_t tgt, Loc* out,
+                                           uint32_t* scr) {
     const int tid = threadIdx.x;
-    const uint32_t c = h[tid];
-    const uint32_t incl = wave_incl_scan(c);
+    uint32_t c[8];
+    uint32_t s = 0;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) { c[i] = h[tid * 8 + i]; s += c[i]; }
+    const uint32_t incl = wave_incl_scan(s);
     const int w = tid / kWave;
     if (__lane_id() == kWave - 1) scr[w] = incl;
     __syncthreads();
-    uint32_t before = base + incl - c;
-    for (int k = 0; k < w; ++k) before += scr[k];
-    if ((int64_t)before <= tgt && tgt < (int64_t)(before + c)) {
-        out->d = tid;
-        out->before = before;
+    uint32_t run = base + incl - s;
+    for (int k = 0; k < w; ++k) run += scr[k];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+        if ((int64_t)run <= tgt && tgt < (int64_t)(run + c[i])) {
+            out->d = tid * 8 + i;
+            out->before = run;
+        }
+        run += c[i];
     }
     __syncthreads();
 }
 
-template <int DK>
+template <int MT, int DKT>
 __global__ __launch_bounds__(kCombThreads) void k_comb_fast(const float* __restrict__ power,
                                                             int32_t n_active, CombArgs ca,
                                                             int32_t i_max,
@@ -373,37 +386,39 @@ __global__ __launch_bounds__(kCombThreads) void k_comb_fast(const float* __restr
                                                             float* __restrict__ snr_all,
                                                             const int32_t* __restrict__ n_dev) {
     extern __shared__ __align__(16) char smem[];
-    float* sP = (float*)smem;                       // [kpad]
-    uint32_t* sCnt = (uint32_t*)(sP + ca.kpad);     // [kpad + 4]
-    __shared__ uint32_t hA[256], hB[256];
+    float* sP = (float*)smem;                       // [kpad]: spectrum, then window maxima
+    uint32_t* sW = (uint32_t*)(sP + ca.kpad);       // [max(kpad + 4, 4096)]: hists, then codes
     __shared__ float sBand[256];
     __shared__ uint16_t sList[kListCap];
     __shared__ double red[kCombThreads / kWave];
     __shared__ uint32_t scr[kCombThreads / kWave];
-    __shared__ Loc l1lo, l1hi, l2lo, l2hi, l3lo, l3hi;
+    __shared__ Loc l1lo, l1hi, l2lo, l2hi;
     __shared__ uint32_t s_nlist;
     __shared__ float s_best[kCombThreads / kWave];
     __shared__ int s_bi[kCombThreads / kWave];
 
     const int K = ca.K;
-    const int dk = DK >= 0 ? DK : ca.dk;
+    const int M = MT > 0 ? MT : ca.M;
+    const int dk = DKT >= 0 ? DKT : ca.dk;
     const int tid = threadIdx.x;
     const int32_t u = blockIdx.x;
     if (u >= n_active || (n_dev && u >= *n_dev)) return;
     const float* row = power + (int64_t)u * K;
+    uint32_t* hA = sW;
+    uint32_t* hB = sW + 2048;
 
-    hA[tid] = 0;
-    hB[tid] = 0;
-    if (tid == 0) {
-        l1lo = l1hi = l2lo = l2hi = l3lo = l3hi = Loc{0, 0};
-        s_nlist = 0;
-    }
-    // ---- P1: load (all loads in flight), sum, exponent histogram ----------
+    // ---- P1: load (all loads in flight), sum, first digit (bits 20..30) ---
     float v[kFastItems];
 #pragma unroll
     for (int i = 0; i < kFastItems; ++i) {
         const int k = tid + i * kCombThreads;
         v[i] = k < K ? row[k] : 0.0f;
+    }
+#pragma unroll
+    for (int i = 0; i < 8; ++i) hA[tid * 8 + i] = 0u;
+    if (tid == 0) {
+        l1lo = l1hi = l2lo = l2hi = Loc{0, 0};
+        s_nlist = 0;
     }
     __syncthreads();
     double sum = 0.0;
@@ -413,19 +428,19 @@ __global__ __launch_bounds__(kCombThreads) void k_comb_fast(const float* __restr
         if (k < K) {
             sP[k] = v[i];
             sum += (double)v[i];
-            atomicAdd(&hA[(__float_as_uint(v[i]) >> 23) & 0xFF], 1u);
+            atomicAdd(&hA[(__float_as_uint(v[i]) >> 20) & 0x7FFu], 1u);
         }
     }
     sum = block_sum_d(sum, red);
     const double mean = sum / (double)K;
     const float floor_v = (float)(ca.eps * mean);
-    locate256(hA, 0, ca.b_lo, &l1lo, scr);
-    locate256(hA, 0, ca.b_hi, &l1hi, scr);
-    const int d1lo = l1lo.d, d1hi = l1hi.d;
-    hA[tid] = 0;
-    hB[tid] = 0;
+    locate2048(hA, 0, ca.b_lo, &l1lo, scr);
+    locate2048(hA, 0, ca.b_hi, &l1hi, scr);
+    const uint32_t d1lo = (uint32_t)l1lo.d, d1hi = (uint32_t)l1hi.d;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) { hA[tid * 8 + i] = 0u; hB[tid * 8 + i] = 0u; }
     __syncthreads();
-    // ---- P2: log-sum (Eq. 7) and second digit ----------------------------
+    // ---- P2: log-sum (Eq. 7) and second digit (bits 9..19) ------------------
     double sl = 0.0;
 #pragma unroll
     for (int i = 0; i < kFastItems; ++i) {
@@ -433,53 +448,34 @@ __global__ __launch_bounds__(kCombThreads) void k_comb_fast(const float* __restr
         if (k < K) {
             sl += (double)__log2f(v[i] > floor_v ? v[i] : floor_v);
             const uint32_t b = __float_as_uint(v[i]);
-            const int d1 = (b >> 23) & 0xFF;
-            if (d1 == d1lo) atomicAdd(&hA[(b >> 15) & 0xFF], 1u);
-            if (d1 == d1hi) atomicAdd(&hB[(b >> 15) & 0xFF], 1u);
+            const uint32_t d1 = (b >> 20) & 0x7FFu;
+            if (d1 == d1lo) atomicAdd(&hA[(b >> 9) & 0x7FFu], 1u);
+            if (d1 == d1hi) atomicAdd(&hB[(b >> 9) & 0x7FFu], 1u);
         }
     }
     sl = block_sum_d(sl, red);
     if (tid == 0) sf_out[u] = mean > 0.0 ? (float)exp2(sl / (double)K - log2(mean)) : 1.0f;
-    locate256(hA, l1lo.before, ca.b_lo, &l2lo, scr);
-    locate256(hB, l1hi.before, ca.b_hi, &l2hi, scr);
-    const uint32_t p2lo = ((uint32_t)d1lo << 8) | (uint32_t)l2lo.d;
-    const uint32_t p2hi = ((uint32_t)d1hi << 8) | (uint32_t)l2hi.d;
-    hA[tid] = 0;
-    hB[tid] = 0;
-    __syncthreads();
-    // ---- P3: third digit --------------------------------------------------
+    locate2048(hA, l1lo.before, ca.b_lo, &l2lo, scr);
+    locate2048(hB, l1hi.before, ca.b_hi, &l2hi, scr);
+    const uint32_t key_lo = (d1lo << 11) | (uint32_t)l2lo.d;
+    const uint32_t key_hi = (d1hi << 11) | (uint32_t)l2hi.d;
+    const uint32_t below_base = l2lo.before;  // values with a 22-bit key below key_lo
+    // ---- P3: classify (temporary codes: 0 below, 1 above, 2 candidate) -----
 #pragma unroll
     for (int i = 0; i < kFastItems; ++i) {
         const int k = tid + i * kCombThreads;
         if (k < K) {
-            const uint32_t b = __float_as_uint(v[i]);
-            const uint32_t p2 = (b >> 15) & 0xFFFF;
-            if (p2 == p2lo) atomicAdd(&hA[(b >> 7) & 0xFF], 1u);
-            if (p2 == p2hi) atomicAdd(&hB[(b >> 7) & 0xFF], 1u);
-        }
-    }
-    __syncthreads();
-    locate256(hA, l2lo.before, ca.b_lo, &l3lo, scr);
-    locate256(hB, l2hi.before, ca.b_hi, &l3hi, scr);
-    const uint32_t key_lo = (p2lo << 8) | (uint32_t)l3lo.d;
-    const uint32_t key_hi = (p2hi << 8) | (uint32_t)l3hi.d;
-    const uint32_t below_base = l3lo.before;
-    // ---- P4: classify; rank the band candidates -------------------------
-    // temporary codes in sCnt: 0 below, 1 above, 2 candidate, 0x100 + idx in band
-#pragma unroll
-    for (int i = 0; i < kFastItems; ++i) {
-        const int k = tid + i * kCombThreads;
-        if (k < K) {
-            const uint32_t kk = __float_as_uint(v[i]) >> 7;
-            uint32_t code = kk < key_lo ? 0u : (kk > key_hi ? 1u : 2u);
+            const uint32_t kk = (__float_as_uint(v[i]) >> 9) & 0x3FFFFFu;
+            const uint32_t code = kk < key_lo ? 0u : (kk > key_hi ? 1u : 2u);
             if (code == 2u) {
                 const uint32_t pos = atomicAdd(&s_nlist, 1u);
                 if (pos < kListCap) sList[pos] = (uint16_t)k;
             }
-            sCnt[k] = code;
+            sW[k] = code;
         }
     }
     __syncthreads();
+    // ---- P4: exact ranks of the candidates (value, bin) -------------------
     const int nL = (int)s_nlist;
     if (nL <= kListCap) {
         for (int a = tid; a < nL; a += kCombThreads) {
@@ -492,22 +488,23 @@ __global__ __launch_bounds__(kCombThreads) void k_comb_fast(const float* __restr
                 r += (vj < vi || (vj == vi && kj < ki)) ? 1u : 0u;
             }
             const int full = (int)(below_base + r);
-            if (full < ca.b_lo) sCnt[ki] = 0u;
-            else if (full > ca.b_hi) sCnt[ki] = 1u;
-            else { sCnt[ki] = 0x100u + (uint32_t)(full - ca.b_lo); sBand[full - ca.b_lo] = vi; }
+            if (full < ca.b_lo) sW[ki] = 0u;
+            else if (full > ca.b_hi) sW[ki] = 1u;
+            else { sW[ki] = 0x100u + (uint32_t)(full - ca.b_lo); sBand[full - ca.b_lo] = vi; }
         }
     } else {
-        // many exact ties: rank each candidate against every candidate bin
+        // many exact ties: rank each candidate bin against all candidate bins
 #pragma unroll 1
         for (int i = 0; i < kFastItems; ++i) {
             const int ki = tid + i * kCombThreads;
-            if (ki >= K || (__float_as_uint(v[i]) >> 7) < key_lo || (__float_as_uint(v[i]) >> 7) > key_hi)
-                continue;
+            if (ki >= K) continue;
+            const uint32_t kki = (__float_as_uint(v[i]) >> 9) & 0x3FFFFFu;
+            if (kki < key_lo || kki > key_hi) continue;
             const float vi = v[i];
             uint32_t r = 0;
             for (int kj = 0; kj < K; ++kj) {
                 const float vj = sP[kj];
-                const uint32_t kk = __float_as_uint(vj) >> 7;
+                const uint32_t kk = (__float_as_uint(vj) >> 9) & 0x3FFFFFu;
                 if (kk >= key_lo && kk <= key_hi && (vj < vi || (vj == vi && kj < ki))) ++r;
             }
             const int full = (int)(below_base + r);
@@ -515,26 +512,34 @@ __global__ __launch_bounds__(kCombThreads) void k_comb_fast(const float* __restr
             if (full < ca.b_lo) code = 0u;
             else if (full > ca.b_hi) code = 1u;
             else { code = 0x100u + (uint32_t)(full - ca.b_lo); sBand[full - ca.b_lo] = vi; }
-            sCnt[ki] = code;
+            sW[ki] = code;
         }
     }
     __syncthreads();
-    // ---- P5: packed prefix counts over contiguous segments ----------------
+    // ---- P5: window maxima in place; packed prefix counts -----------------
     {
         const int seg = (K + kCombThreads - 1) / kCombThreads;  // <= 16
         const int k0 = tid * seg;
+        float wm[kFastItems];
         uint32_t code[kFastItems];
         uint32_t s = 0;
 #pragma unroll
         for (int j = 0; j < kFastItems; ++j) {
             const int k = k0 + j;
-            code[j] = (j < seg && k < K) ? sCnt[k] : 1u;
+            const bool in = j < seg && k < K;
+            code[j] = in ? sW[k] : 1u;
             s += code[j] == 0u ? 1u : (code[j] >= 0x100u ? 0x1000u : 0u);
+            float mx = 0.0f;
+            if (in && k >= dk && k + dk <= K - 1) {
+                mx = sP[k - dk];
+                for (int q = 1; q <= 2 * dk; ++q) mx = fmaxf(mx, sP[k - dk + q]);
+            }
+            wm[j] = mx;
         }
         const uint32_t incl = wave_incl_scan(s);
         const int w = tid / kWave;
         if (__lane_id() == kWave - 1) scr[w] = incl;
-        __syncthreads();
+        __syncthreads();  // every window read of sP is done before sP is overwritten
         uint32_t run = incl - s;
         for (int q = 0; q < w; ++q) run += scr[q];
 #pragma unroll
@@ -542,16 +547,16 @@ __global__ __launch_bounds__(kCombThreads) void k_comb_fast(const float* __restr
             const int k = k0 + j;
             if (j < seg && k < K) {
                 const uint32_t rk = code[j] >= 0x100u ? (code[j] - 0x100u) : 0xFFu;
-                sCnt[k] = run | (rk << 24);
+                sW[k] = run | (rk << 24);
+                sP[k] = wm[j];
                 run += code[j] == 0u ? 1u : (code[j] >= 0x100u ? 0x1000u : 0u);
             }
         }
-        if (k0 < K && k0 + seg >= K) sCnt[K] = run;
+        if (k0 < K && k0 + seg >= K) sW[K] = run;
     }
     __syncthreads();
     // ---- P6: candidates (Eq. 8-11) ----------------------------------------
     const float fden_floor = (float)(ca.eps * mean);
-    const int hmax = ca.M * (2 * dk + 1);
     float best = 0.0f;
     int best_i = -1;
     for (int i = dk + tid; i <= i_max; i += kCombThreads) {
@@ -561,7 +566,9 @@ __global__ __launch_bounds__(kCombThreads) void k_comb_fast(const float* __restr
             return (int)floor(num / (double)ca.df + 0.5);
         };
         int mv = 0;
-        for (int m = 1; m <= ca.M; ++m) {
+#pragma unroll
+        for (int m = 1; m <= (MT > 0 ? MT : 32); ++m) {
+            if (m > M) break;
             if (centre(m) + dk > K - 1) break;
             mv = m;
         }
@@ -569,25 +576,31 @@ __global__ __launch_bounds__(kCombThreads) void k_comb_fast(const float* __restr
         if (mv >= ca.h_min) {
             float smax = 0.0f;
             int hsize = 0;
-            uint32_t below = 0, inb = 0;
+            uint32_t below = 0;
+            int nin = 0;
+            bool spill = false;
+            int inr[kInbCap];
             int prev_hi = -1;
-            for (int m = 1; m <= mv; ++m) {
-                const int cm = centre(m);
-                float mx = sP[cm - dk];
-                if (DK >= 0) {
 #pragma unroll
-                    for (int k = 1; k <= 2 * (DK >= 0 ? DK : 0); ++k) mx = fmaxf(mx, sP[cm - dk + k]);
-                } else {
-                    for (int k = 1; k <= 2 * dk; ++k) mx = fmaxf(mx, sP[cm - dk + k]);
-                }
-                smax += mx;
+            for (int m = 1; m <= (MT > 0 ? MT : 32); ++m) {
+                if (m > mv) break;
+                const int cm = centre(m);
+                smax += sP[cm];
                 const int lo = (cm - dk) > prev_hi + 1 ? (cm - dk) : prev_hi + 1;
                 const int hi = cm + dk;
                 if (lo <= hi) {
                     hsize += hi - lo + 1;
-                    const uint32_t d = (sCnt[hi + 1] & 0xFFFFFu) - (sCnt[lo] & 0xFFFFFu);
+                    const uint32_t d = (sW[hi + 1] & 0xFFFFFu) - (sW[lo] & 0xFFFFFu);
                     below += d & 0xFFFu;
-                    inb += d >> 12;
+                    if (d >> 12) {
+                        for (int k = lo; k <= hi; ++k) {
+                            const uint32_t rk = sW[k] >> 24;
+                            if (rk != 0xFFu) {
+                                if (nin < kInbCap) inr[nin++] = (int)rk;
+                                else spill = true;
+                            }
+                        }
+                    }
                 }
                 prev_hi = hi;
             }
@@ -596,27 +609,37 @@ __global__ __launch_bounds__(kCombThreads) void k_comb_fast(const float* __restr
             float med = 0.0f;
             if (nc > 0) {
                 const int r = (nc - 1) / 2;
-                int q = r + (int)below;
-                if (inb > 0) {
-                    for (int iter = 0; iter <= hmax + 1; ++iter) {
+                // band index of the median: q = r + below + #(in-band window bins <= q)
+                int q = r + (int)below - ca.b_lo;
+                if (!spill) {
+                    for (int iter = 0; iter <= kInbCap; ++iter) {
                         int extra = 0;
-                        int ph = -1;
+                        for (int j = 0; j < nin; ++j) extra += inr[j] <= q ? 1 : 0;
+                        const int qn = r + (int)below - ca.b_lo + extra;
+                        if (qn == q) break;
+                        q = qn;
+                    }
+                } else {
+                    const int hmax = M * (2 * dk + 1);
+                    for (int iter = 0; iter <= hmax + 1; ++iter) {
+                        int extra = 0, ph = -1;
                         for (int m = 1; m <= mv; ++m) {
                             const int cm = centre(m);
                             const int lo = (cm - dk) > ph + 1 ? (cm - dk) : ph + 1;
                             for (int k = lo; k <= cm + dk; ++k) {
-                                const uint32_t rk = sCnt[k] >> 24;
-                                if (rk != 0xFFu && ca.b_lo + (int)rk <= q) ++extra;
+                                const uint32_t rk = sW[k] >> 24;
+                                if (rk != 0xFFu && (int)rk <= q) ++extra;
                             }
                             ph = cm + dk;
                         }
-                        const int qn = r + (int)below + extra;
+                        const int qn = r + (int)below - ca.b_lo + extra;
                         if (qn == q) break;
                         q = qn;
                     }
                 }
-                q = q < ca.b_lo ? ca.b_lo : (q > ca.b_hi ? ca.b_hi : q);
-                med = sBand[q - ca.b_lo];
+                const int bw = ca.b_hi - ca.b_lo;
+                q = q < 0 ? 0 : (q > bw ? bw : q);
+                med = sBand[q];
             }
             const float den = med > fden_floor ? med : fden_floor;
             snr = den > 0.0f ? N / den : 0.0f;
@@ -708,24 +731,18 @@ int comb_run(const float* power, int32_t n_active, const int32_t* n_dev, const d
     }
     const int bw = ca.b_hi - ca.b_lo + 1;
     if (ca.K <= 4095 && bw <= 254) {
-        const size_t lds = (size_t)ca.kpad * 4 + (size_t)(ca.kpad + 4) * 4;
-        switch (ca.dk) {
-#define DDHF_COMB_CASE(D)                                                                       \
-    case D:                                                                                     \
-        hipLaunchKernelGGL(k_comb_fast<D>, dim3((unsigned)n_active), dim3(kCombThreads), lds, s, \
-                           power, n_active, ca, i_max, sf, snr_best, bin_best, snr_all, n_dev); \
-        break;
-            DDHF_COMB_CASE(0)
-            DDHF_COMB_CASE(1)
-            DDHF_COMB_CASE(2)
-            DDHF_COMB_CASE(3)
-            DDHF_COMB_CASE(4)
-#undef DDHF_COMB_CASE
-            default:
-                hipLaunchKernelGGL(k_comb_fast<-1>, dim3((unsigned)n_active), dim3(kCombThreads),
-                                   lds, s, power, n_active, ca, i_max, sf, snr_best, bin_best,
-                                   snr_all, n_dev);
-        }
+        const int wwords = (ca.kpad + 4) > 4096 ? (ca.kpad + 4) : 4096;
+        const size_t lds = (size_t)ca.kpad * 4 + (size_t)wwords * 4;
+        const dim3 gr((unsigned)n_active), bl(kCombThreads);
+        if (ca.M == 4 && ca.dk == 3)
+            hipLaunchKernelGGL((k_comb_fast<4, 3>), gr, bl, lds, s, power, n_active, ca, i_max, sf,
+                               snr_best, bin_best, snr_all, n_dev);
+        else if (ca.M == 5 && ca.dk == 3)
+            hipLaunchKernelGGL((k_comb_fast<5, 3>), gr, bl, lds, s, power, n_active, ca, i_max, sf,
+                               snr_best, bin_best, snr_all, n_dev);
+        else
+            hipLaunchKernelGGL((k_comb_fast<-1, -1>), gr, bl, lds, s, power, n_active, ca, i_max,
+                               sf, snr_best, bin_best, snr_all, n_dev);
         DDHF_LAUNCH_CHECK();
         return DDHF_OK;
     }

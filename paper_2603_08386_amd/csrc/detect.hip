@@ -20,6 +20,7 @@ constexpr int kCap = DDHF_DETECT_MAX_CANDIDATES;
 
 struct DetectWs {
     int32_t *x0, *y0, *x1, *y1, *npx, *pbin;
+    float* psnr;
     unsigned long long* rep;
     ddhf_box_t* cand;
     int32_t* ctr;  // [0] candidates, [1] dropped
@@ -32,6 +33,7 @@ static void detect_layout(Arena& ar, int64_t npix, DetectWs* d) {
     d->y1 = ar.take<int32_t>(npix);
     d->npx = ar.take<int32_t>(npix);
     d->pbin = ar.take<int32_t>(npix);
+    d->psnr = ar.take<float>(npix);
     d->rep = ar.take<unsigned long long>(npix);
     d->cand = ar.take<ddhf_box_t>(kCap);
     d->ctr = ar.take<int32_t>(4);
@@ -96,15 +98,16 @@ __global__ void k_det_mask(const int32_t* __restrict__ active, const int32_t* __
         d.npx[q] = 0;
         d.rep[q] = 0ull;
         d.pbin[q] = bin[u];
+        d.psnr[q] = snr[u];
     }
 }
 
-__global__ void k_det_union(const int32_t* __restrict__ active, int32_t n_active, int32_t W,
-                            int32_t H, const uint8_t* __restrict__ mask, int32_t* labels, const int32_t* __restrict__ n_dev) {
-    const int32_t u = blockIdx.x * blockDim.x + threadIdx.x;
-    if (u >= n_active || (n_dev && u >= *n_dev)) return;
-    const int32_t q = active[u];
-    if (!mask[q]) return;
+// The kernels below walk the pixels in raster order (whatever the order of the
+// active list), so a wavefront covers neighbouring pixels.
+__global__ void k_det_union(int32_t npix, int32_t W, const uint8_t* __restrict__ mask,
+                            int32_t* labels) {
+    const int32_t q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= npix || !mask[q]) return;
     const int32_t x = q % W, y = q / W;
     // half neighbourhood: W, NW, N, NE
     if (x > 0 && mask[q - 1]) uf_union(labels, q, q - 1);
@@ -114,15 +117,11 @@ __global__ void k_det_union(const int32_t* __restrict__ active, int32_t n_active
         if (mask[r]) uf_union(labels, q, r);
         if (x + 1 < W && mask[r + 1]) uf_union(labels, q, r + 1);
     }
-    (void)H;
 }
 
-__global__ void k_det_compress(const int32_t* __restrict__ active, int32_t n_active,
-                               const uint8_t* __restrict__ mask, int32_t* labels, const int32_t* __restrict__ n_dev) {
-    const int32_t u = blockIdx.x * blockDim.x + threadIdx.x;
-    if (u >= n_active || (n_dev && u >= *n_dev)) return;
-    const int32_t q = active[u];
-    if (!mask[q]) return;
+__global__ void k_det_compress(int32_t npix, const uint8_t* __restrict__ mask, int32_t* labels) {
+    const int32_t q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= npix || !mask[q]) return;
     const int32_t r = uf_find(labels, q);
     __hip_atomic_store(&labels[q], r, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
@@ -130,18 +129,13 @@ __global__ void k_det_compress(const int32_t* __restrict__ active, int32_t n_act
 // Box accumulation.  Large components make many lanes share one root, so a
 // wavefront whose mask lanes all share the first lane's root reduces in
 // registers and issues one atomic per field; other waves use per-lane atomics.
-__global__ __launch_bounds__(256) void k_det_accum(const int32_t* __restrict__ active,
-                                                   const float* __restrict__ snr, int32_t n_active,
-                                                   int32_t W, const uint8_t* __restrict__ mask,
+__global__ __launch_bounds__(256) void k_det_accum(int32_t npix, int32_t W,
+                                                   const uint8_t* __restrict__ mask,
                                                    const int32_t* __restrict__ labels,
-                                                   DetectWs d, const int32_t* __restrict__ n_dev) {
-    const int32_t u = blockIdx.x * blockDim.x + threadIdx.x;
-    int32_t q = -1, r = -1;
-    if (u < n_active && !(n_dev && u >= *n_dev)) {
-        q = active[u];
-        if (mask[q]) r = labels[q];
-        else q = -1;
-    }
+                                                   DetectWs d) {
+    const int32_t q = blockIdx.x * blockDim.x + threadIdx.x;
+    int32_t r = -1;
+    if (q < npix && mask[q]) r = labels[q];
     const bool on = r >= 0;
     const uint64_t pend = __ballot(on);
     if (pend == 0) return;
@@ -150,7 +144,7 @@ __global__ __launch_bounds__(256) void k_det_accum(const int32_t* __restrict__ a
     const uint64_t same = __ballot(on && r == r0);
     const int32_t x = on ? q % W : 0x7FFFFFFF, y = on ? q / W : 0x7FFFFFFF;
     const unsigned long long key =
-        on ? (((unsigned long long)__float_as_uint(snr[u]) << 32) |
+        on ? (((unsigned long long)__float_as_uint(d.psnr[q]) << 32) |
               (unsigned long long)(0xFFFFFFFFu - (uint32_t)q))
            : 0ull;
     if (same == pend) {
@@ -185,13 +179,10 @@ __global__ __launch_bounds__(256) void k_det_accum(const int32_t* __restrict__ a
     atomicMax(&d.rep[r], key);
 }
 
-__global__ void k_det_collect(const int32_t* __restrict__ active, int32_t n_active,
-                              const uint8_t* __restrict__ mask, const int32_t* __restrict__ labels,
-                              int32_t a_min, DetectWs d, const int32_t* __restrict__ n_dev) {
-    const int32_t u = blockIdx.x * blockDim.x + threadIdx.x;
-    if (u >= n_active || (n_dev && u >= *n_dev)) return;
-    const int32_t q = active[u];
-    if (!mask[q] || labels[q] != q) return;
+__global__ void k_det_collect(int32_t npix, const uint8_t* __restrict__ mask,
+                              const int32_t* __restrict__ labels, int32_t a_min, DetectWs d) {
+    const int32_t q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= npix || !mask[q] || labels[q] != q) return;
     const int64_t area = (int64_t)(d.x1[q] - d.x0[q] + 1) * (int64_t)(d.y1[q] - d.y0[q] + 1);
     if (area < a_min) return;
     const int32_t slot = atomicAdd(&d.ctr[0], 1);
@@ -487,15 +478,15 @@ int detect_run(const int32_t* active, const int32_t* row_ptr, const float* sf,
         hipLaunchKernelGGL(k_det_mask, gb, dim3(256), 0, s, active, row_ptr, sf, snr_best, bin_best,
                            n_active, ma, mask, labels, d, n_dev);
         DDHF_LAUNCH_CHECK();
-        hipLaunchKernelGGL(k_det_union, gb, dim3(256), 0, s, active, n_active, W, H, mask, labels, n_dev);
+        const dim3 gp(blocks_for(npix, 256));
+        hipLaunchKernelGGL(k_det_union, gp, dim3(256), 0, s, (int32_t)npix, W, mask, labels);
         DDHF_LAUNCH_CHECK();
-        hipLaunchKernelGGL(k_det_compress, gb, dim3(256), 0, s, active, n_active, mask, labels, n_dev);
+        hipLaunchKernelGGL(k_det_compress, gp, dim3(256), 0, s, (int32_t)npix, mask, labels);
         DDHF_LAUNCH_CHECK();
-        hipLaunchKernelGGL(k_det_accum, gb, dim3(256), 0, s, active, snr_best, n_active, W, mask,
-                           labels, d, n_dev);
+        hipLaunchKernelGGL(k_det_accum, gp, dim3(256), 0, s, (int32_t)npix, W, mask, labels, d);
         DDHF_LAUNCH_CHECK();
-        hipLaunchKernelGGL(k_det_collect, gb, dim3(256), 0, s, active, n_active, mask, labels,
-                           prm->a_min, d, n_dev);
+        hipLaunchKernelGGL(k_det_collect, gp, dim3(256), 0, s, (int32_t)npix, mask, labels,
+                           prm->a_min, d);
         DDHF_LAUNCH_CHECK();
     }
     hipLaunchKernelGGL(k_det_merge, dim3(1), dim3(kMergeThreads), merge_lds_bytes(), s, d,

@@ -135,7 +135,7 @@ __global__ __launch_bounds__(kRadixThreads) void k_radix_scatter(
     const uint32_t* __restrict__ kin, const uint32_t* __restrict__ vin,
     uint32_t* __restrict__ kout, uint32_t* __restrict__ vout, int64_t n_host,
     const int32_t* __restrict__ n_dev, int shift, int bits, const uint32_t* __restrict__ goff,
-    int n_tiles) {
+    int n_tiles, const uint32_t* __restrict__ v2in, uint32_t* __restrict__ v2out) {
     __shared__ uint32_t cnt[kRadixWaves][256];
     __shared__ uint32_t woff[kRadixWaves][256];
     const int tid = threadIdx.x;
@@ -147,7 +147,7 @@ __global__ __launch_bounds__(kRadixThreads) void k_radix_scatter(
     const uint32_t mask = (1u << bits) - 1u;
     const int64_t wbase = (int64_t)blockIdx.x * kRadixTile + (int64_t)w * kWaveSpan;
     const uint64_t lt = lanemask_lt();
-    uint32_t key[kRadixItems], val[kRadixItems], rank[kRadixItems];
+    uint32_t key[kRadixItems], val[kRadixItems], val2[kRadixItems], rank[kRadixItems];
     volatile uint32_t* wc = cnt[w];
 #pragma unroll
     for (int it = 0; it < kRadixItems; ++it) {
@@ -155,6 +155,7 @@ __global__ __launch_bounds__(kRadixThreads) void k_radix_scatter(
         const bool valid = idx < n;
         const uint32_t k = valid ? kin[idx] : 0u;
         const uint32_t v = valid ? vin[idx] : 0u;
+        val2[it] = (valid && v2in) ? v2in[idx] : 0u;
         const uint32_t d = (k >> shift) & mask;
         uint64_t m = __ballot(valid);
         for (int b = 0; b < bits; ++b) {
@@ -190,6 +191,7 @@ __global__ __launch_bounds__(kRadixThreads) void k_radix_scatter(
             const uint32_t pos = goff[(int64_t)d * n_tiles + blockIdx.x] + woff[w][d] + rank[it];
             kout[pos] = key[it];
             vout[pos] = val[it];
+            if (v2out) v2out[pos] = val2[it];
         }
     }
 }
@@ -220,11 +222,12 @@ static RadixWs radix_ws_take(Arena& ar, int64_t n) {
 // (k0, v0) and (k1, v1); *in_first tells where the result ended up.
 int radix_sort_pairs(uint32_t* k0, uint32_t* v0, uint32_t* k1, uint32_t* v1,
                             int64_t n_bound, const int32_t* n_dev, int bit0, int nbits,
-                            const RadixWs& rw, hipStream_t s, bool* in_first) {
+                            const RadixWs& rw, hipStream_t s, bool* in_first,
+                            uint32_t* w0 = nullptr, uint32_t* w1 = nullptr) {
     *in_first = true;
     if (n_bound <= 0 || nbits <= 0) return DDHF_OK;
     const int n_tiles = (int)((n_bound + kRadixTile - 1) / kRadixTile);
-    uint32_t *ka = k0, *va = v0, *kb = k1, *vb = v1;
+    uint32_t *ka = k0, *va = v0, *kb = k1, *vb = v1, *wa = w0, *wb = w1;
     for (int b = bit0; b < bit0 + nbits; b += 8) {
         const int bits = (bit0 + nbits - b) < 8 ? (bit0 + nbits - b) : 8;
         hipLaunchKernelGGL(k_radix_hist, dim3(n_tiles), dim3(kRadixThreads), 0, s, ka, n_bound,
@@ -233,11 +236,12 @@ int radix_sort_pairs(uint32_t* k0, uint32_t* v0, uint32_t* k1, uint32_t* v1,
         int rc = scan_exclusive_u32(rw.ghist, rw.goff, (int64_t)n_tiles << bits, rw.scan_ws, s);
         if (rc) return rc;
         hipLaunchKernelGGL(k_radix_scatter, dim3(n_tiles), dim3(kRadixThreads), 0, s, ka, va, kb,
-                           vb, n_bound, n_dev, b, bits, rw.goff, n_tiles);
+                           vb, n_bound, n_dev, b, bits, rw.goff, n_tiles, wa, wb);
         DDHF_LAUNCH_CHECK();
         uint32_t* t;
         t = ka; ka = kb; kb = t;
         t = va; va = vb; vb = t;
+        t = wa; wa = wb; wb = t;
         *in_first = !*in_first;
     }
     return DDHF_OK;
@@ -279,7 +283,7 @@ __global__ __launch_bounds__(kPrepThreads) void k_prepare(
     const uint16_t* __restrict__ x, const uint16_t* __restrict__ y, const int8_t* __restrict__ p,
     const int64_t* __restrict__ t, int64_t n, int32_t W, int32_t H, int64_t t0, int64_t T_w,
     uint32_t* __restrict__ key_pix, uint32_t* __restrict__ key_t, uint32_t* __restrict__ vals,
-    ddhf_counters_t* counters) {
+    uint32_t* __restrict__ tp, ddhf_counters_t* counters) {
     __shared__ uint32_t red[5][kPrepThreads / kWave];
     uint32_t c[5] = {0, 0, 0, 0, 0};  // kept, window, sensor, polarity, unsorted
     const uint32_t npix = (uint32_t)W * (uint32_t)H;
@@ -296,8 +300,10 @@ __global__ __launch_bounds__(kPrepThreads) void k_prepare(
             const int cat = !win ? 1 : (!sen ? 2 : (!pol ? 3 : 0));
             c[cat] += 1u;
             key_pix[i] = cat == 0 ? (uint32_t)y[i] * (uint32_t)W + x[i] : npix;
-            if (key_t) key_t[i] = cat == 0 ? (uint32_t)(ti - t0) : 0u;
+            const uint32_t tr = cat == 0 ? (uint32_t)(ti - t0) : 0u;
+            if (key_t) key_t[i] = tr;
             vals[i] = (uint32_t)i;
+            tp[i] = tr | (pi > 0 ? 0u : 0x80000000u);  // t_rel < 2^31: sign in the top bit
             if (i > 0 && ti < t[i - 1]) c[4] += 1u;
         }
     }
@@ -344,22 +350,26 @@ __global__ __launch_bounds__(256) void k_count_runs(const uint32_t* __restrict__
     }
 }
 
-__global__ __launch_bounds__(256) void k_gather_events(
-    const uint32_t* __restrict__ vals, const uint32_t* __restrict__ keys, int64_t n, uint32_t npix,
-    const int8_t* __restrict__ p, const int64_t* __restrict__ t, const float* __restrict__ w,
-    int64_t t0, uint32_t* __restrict__ t_rel, float* __restrict__ a, int32_t* __restrict__ perm) {
+// Writes the CSR event arrays from the sorted (index, t_rel | sign) values;
+// only an optional per-event weight is gathered through the permutation.
+__global__ __launch_bounds__(256) void k_finish_events(
+    const uint32_t* __restrict__ vals, const uint32_t* __restrict__ tp,
+    const uint32_t* __restrict__ keys, int64_t n, uint32_t npix, const float* __restrict__ w,
+    uint32_t* __restrict__ t_rel, float* __restrict__ a, int32_t* __restrict__ perm) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n || keys[i] >= npix) return;
     const uint32_t src = vals[i];
+    const uint32_t v = tp[i];
     perm[i] = (int32_t)src;
-    t_rel[i] = (uint32_t)(t[src] - t0);
-    const float sgn = p[src] > 0 ? 1.0f : -1.0f;
+    t_rel[i] = v & 0x7FFFFFFFu;
+    const float sgn = (v >> 31) ? -1.0f : 1.0f;
     a[i] = w ? sgn * w[src] : sgn;
 }
 
 static int index_layout(Arena& ar, int64_t n, int32_t W, int32_t H, int64_t T_w, int32_t flags,
                         uint32_t** key_pix, uint32_t** key_t, uint32_t** vals, uint32_t** k1,
-                        uint32_t** v1, uint32_t** counts, void** scan_ws, RadixWs* rw) {
+                        uint32_t** v1, uint32_t** counts, void** scan_ws, RadixWs* rw,
+                        uint32_t** tp0, uint32_t** tp1) {
     const int64_t npix = (int64_t)W * H;
     const int64_t nn = n > 0 ? n : 1;
     *key_pix = ar.take<uint32_t>(nn);
@@ -370,6 +380,8 @@ static int index_layout(Arena& ar, int64_t n, int32_t W, int32_t H, int64_t T_w,
     *counts = ar.take<uint32_t>(npix + 1);
     *scan_ws = ar.take<char>(scan_ws_bytes(npix + 1));
     *rw = radix_ws_take(ar, nn);
+    *tp0 = ar.take<uint32_t>(nn);
+    *tp1 = ar.take<uint32_t>(nn);
     (void)T_w;
     return DDHF_OK;
 }
@@ -384,10 +396,10 @@ extern "C" int ddhf_build_pixel_index_workspace_size(int64_t n, int32_t W, int32
     if (!bytes || n < 0 || W <= 0 || H <= 0 || (int64_t)W * H >= INT32_MAX || T_w_us <= 0)
         return DDHF_EINVAL;
     Arena ar(nullptr, 0);
-    uint32_t *a, *b, *c, *d, *e, *f;
+    uint32_t *a, *b, *c, *d, *e, *f, *t0p, *t1p;
     void* g;
     RadixWs rw;
-    index_layout(ar, n, W, H, T_w_us, flags, &a, &b, &c, &d, &e, &f, &g, &rw);
+    index_layout(ar, n, W, H, T_w_us, flags, &a, &b, &c, &d, &e, &f, &g, &rw, &t0p, &t1p);
     *bytes = ar.used;
     return DDHF_OK;
 }
@@ -404,11 +416,11 @@ extern "C" int ddhf_build_pixel_index(const uint16_t* x, const uint16_t* y, cons
     if (n > 0 && (!x || !y || !p || !t_us || !t_rel || !a || !perm)) return DDHF_EINVAL;
     hipStream_t s = as_stream(stream);
     Arena ar(ws, ws_bytes);
-    uint32_t *key_pix, *key_t, *vals, *k1, *v1, *counts;
+    uint32_t *key_pix, *key_t, *vals, *k1, *v1, *counts, *tp0, *tp1;
     void* scan_ws;
     RadixWs rw;
     index_layout(ar, n, W, H, T_w_us, flags, &key_pix, &key_t, &vals, &k1, &v1, &counts, &scan_ws,
-                 &rw);
+                 &rw, &tp0, &tp1);
     if (!ar.fits()) return DDHF_ENOSPACE;
     const int64_t npix = (int64_t)W * H;
     int rc;
@@ -419,36 +431,40 @@ extern "C" int ddhf_build_pixel_index(const uint16_t* x, const uint16_t* y, cons
     if (n > 0) {
         hipLaunchKernelGGL(k_prepare, dim3(blocks_for(n, kPrepThreads * kPrepItems)),
                            dim3(kPrepThreads), 0, s, x, y, p, t_us, n,
-                           W, H, t0_us, T_w_us, key_pix, key_t, vals, counters);
+                           W, H, t0_us, T_w_us, key_pix, key_t, vals, tp0, counters);
         DDHF_LAUNCH_CHECK();
     }
     uint32_t* keys = key_pix;
+    uint32_t* tps = tp0;
     if (n > 0 && key_t) {
         // unsorted input: stable sort by time first, then by pixel
         bool first;
         rc = radix_sort_pairs(key_t, vals, k1, v1, n, nullptr, 0, bits_for((uint64_t)T_w_us - 1),
-                              rw, s, &first);
+                              rw, s, &first, tp0, tp1);
         if (rc) return rc;
         uint32_t* vs = first ? vals : v1;
+        uint32_t* ts = first ? tp0 : tp1;
         uint32_t* kd = first ? k1 : key_t;  // free key buffer
         hipLaunchKernelGGL(k_gather_keys, dim3(blocks_for(n, 256)), dim3(256), 0, s, vs, key_pix,
                            kd, n);
         DDHF_LAUNCH_CHECK();
-        // continue with (kd, vs); pick the other pair as the ping-pong partner
         uint32_t* ko = first ? key_t : k1;
         uint32_t* vo = first ? v1 : vals;
+        uint32_t* to = first ? tp1 : tp0;
         rc = radix_sort_pairs(kd, vs, ko, vo, n, nullptr, 0, bits_for((uint64_t)npix), rw, s,
-                              &first);
+                              &first, ts, to);
         if (rc) return rc;
         keys = first ? kd : ko;
         vals = first ? vs : vo;
+        tps = first ? ts : to;
     } else if (n > 0) {
         bool first;
         rc = radix_sort_pairs(key_pix, vals, k1, v1, n, nullptr, 0, bits_for((uint64_t)npix), rw,
-                              s, &first);
+                              s, &first, tp0, tp1);
         if (rc) return rc;
         keys = first ? key_pix : k1;
         vals = first ? vals : v1;
+        tps = first ? tp0 : tp1;
     }
     rc = fill_u32(counts, 0u, npix + 1, s);
     if (rc) return rc;
@@ -460,8 +476,8 @@ extern "C" int ddhf_build_pixel_index(const uint16_t* x, const uint16_t* y, cons
     rc = scan_exclusive_u32(counts, (uint32_t*)row_ptr, npix + 1, scan_ws, s);
     if (rc) return rc;
     if (n > 0) {
-        hipLaunchKernelGGL(k_gather_events, dim3(blocks_for(n, 256)), dim3(256), 0, s, vals, keys,
-                           n, (uint32_t)npix, p, t_us, w, t0_us, t_rel, a, perm);
+        hipLaunchKernelGGL(k_finish_events, dim3(blocks_for(n, 256)), dim3(256), 0, s, vals, tps,
+                           keys, n, (uint32_t)npix, w, t_rel, a, perm);
         DDHF_LAUNCH_CHECK();
     }
     return DDHF_OK;

@@ -49,18 +49,62 @@ static GridDev grid_dev(const ddhf_grid_t* g) {
     return d;
 }
 
-// (x mod Q) for 0 <= x < 2^52, with the quotient estimated in FP64.
-__device__ __forceinline__ uint32_t mod_q_small(double x, double Qd, double invQ) {
-    double q = floor(x * invQ);
-    double r = x - q * Qd;  // exact: integers below 2^53
-    if (r < 0.0) r += Qd;
-    if (r >= Qd) r -= Qd;
-    return (uint32_t)r;
+// ---------------------------------------------------------------------------
+// Fixed-point phases.  An exact residue r < Q becomes the 32-bit fraction
+// floor(r 2^32 / Q) of a revolution; the per-bin step D becomes a 48-bit
+// fraction F = floor(D 2^48 / Q) held as q1 = F >> 16 (split in 16-bit halves)
+// and q2 = F & 0xFFFF.  The phase of bin offset m is then the 32-bit value
+//     phi = phiA + m q1 + ((m q2) >> 16)   (mod 2^32),
+// formed with 24-bit integer multiply-adds; for m < 2^10 its error is below
+// 2^-31 revolutions.
+// ---------------------------------------------------------------------------
+struct Frac {
+    uint32_t phiA, q1lo, q1hi, q2;
+};
+
+__device__ __forceinline__ Frac make_frac(uint32_t A, uint32_t D, uint32_t Q) {
+    Frac f;
+    f.phiA = (uint32_t)(((uint64_t)A << 32) / Q);
+    const uint64_t xd = (uint64_t)D << 32;
+    const uint32_t q1 = (uint32_t)(xd / Q);
+    const uint64_t r1 = xd % Q;
+    f.q1lo = q1 & 0xFFFFu;
+    f.q1hi = q1 >> 16;
+    f.q2 = (uint32_t)((r1 << 16) / Q);
+    return f;
 }
 
-// Residue (in revolutions, [-0.5, 0.5)) -> (cos, sin) of 2 pi rev.
-__device__ __forceinline__ void cis_rev(float rev, float& c, float& s) {
-    sincospif(2.0f * rev, &s, &c);
+__device__ __forceinline__ uint32_t frac_phase(uint32_t phiA, uint32_t q1lo, uint32_t q1hi,
+                                               uint32_t q2, uint32_t m) {
+    // operands below 2^16 and 2^10: the products map onto 24-bit multiply-adds
+    const uint32_t mm = m & 0x3FFu;
+    const uint32_t t = mm * (q1lo & 0xFFFFu) + phiA;
+    const uint32_t u = mm * (q1hi & 0xFFFFu);
+    const uint32_t v = mm * (q2 & 0xFFFFu);
+    return t + (u << 16) + (v >> 16);
+}
+
+// sin, cos of 2 pi phi / 2^32: nearest quarter turn from the top bits, Taylor
+// polynomials on |y| <= pi/4 (truncation below 2.5e-8), quadrant by swaps and
+// sign flips.
+__device__ __forceinline__ void sincos_fixed(uint32_t phi, float& s, float& c) {
+    const uint32_t t = phi + 0x20000000u;
+    const uint32_t q = t >> 30;
+    const int32_t yi = (int32_t)(t & 0x3FFFFFFFu) - 0x20000000;
+    const float y = (float)yi * 1.46291807926715968e-09f;  // 2 pi / 2^32
+    const float y2 = y * y;
+    float sp = fmaf(y2, 2.75573192e-06f, -1.98412698e-04f);
+    sp = fmaf(sp, y2, 8.33333333e-03f);
+    sp = fmaf(sp, y2, -1.66666667e-01f);
+    const float sv = fmaf(y * y2, sp, y);
+    float cp = fmaf(y2, 2.48015873e-05f, -1.38888889e-03f);
+    cp = fmaf(cp, y2, 4.16666667e-02f);
+    cp = fmaf(cp, y2, -0.5f);
+    const float cv = fmaf(cp, y2, 1.0f);
+    const float as = (q & 1u) ? cv : sv;
+    const float ac = (q & 1u) ? sv : cv;
+    s = (q & 2u) ? -as : as;
+    c = ((q + 1u) & 2u) ? -ac : ac;
 }
 
 struct Unit {
@@ -116,11 +160,13 @@ __device__ __forceinline__ bool next_unit(const WorkDev& wk, const int32_t* row_
 }
 
 struct EvStage {
-    uint32_t A, D;
-    float a, wc, ws;
+    uint32_t phiA, q1lo, q1hi, q2;
+    float a, wc, ws, pad;
 };
 
-// Stages events [c0, c0 + 64) of a unit: exact residues and step phasor.
+// Stages events [c0, c0 + 64) of a unit: exact residues A = f_tile t mod Q and
+// D = df t mod Q as fixed-point fractions, and the step phasor
+// exp(2 pi i (step_mul D mod Q) / Q) from the exact residue in FP64.
 __device__ __forceinline__ void stage_event(EvStage* st, int lane, int32_t c0, int32_t end,
                                             const uint32_t* t_rel, const float* av,
                                             uint64_t f_tile, const GridDev& g, uint32_t step_mul) {
@@ -128,9 +174,15 @@ __device__ __forceinline__ void stage_event(EvStage* st, int lane, int32_t c0, i
     if (e < end) {
         const uint64_t t = t_rel[e];
         EvStage s;
-        s.A = (uint32_t)((f_tile * t) % g.Q);
-        s.D = (uint32_t)(((uint64_t)g.df * t) % g.Q);
-        const uint32_t S = (uint32_t)(((uint64_t)s.D * step_mul) % g.Q);
+        const uint32_t A = (uint32_t)((f_tile * t) % g.Q);
+        const uint32_t D = (uint32_t)(((uint64_t)g.df * t) % g.Q);
+        const Frac f = make_frac(A, D, g.Q);
+        s.phiA = f.phiA;
+        s.q1lo = f.q1lo;
+        s.q1hi = f.q1hi;
+        s.q2 = f.q2;
+        s.pad = 0.0f;
+        const uint32_t S = (uint32_t)(((uint64_t)D * step_mul) % g.Q);
         double rs = (double)S * g.invQ;
         if (rs >= 0.5) rs -= 1.0;
         double sn, cs;
@@ -151,7 +203,6 @@ __global__ __launch_bounds__(64) void k_ndft_valu(const int32_t* __restrict__ ro
                                                   float* __restrict__ power, WorkDev wk) {
     __shared__ EvStage st[64];
     const int lane = threadIdx.x;
-    const double Qd = (double)g.Q;
     int64_t iter = 0;
     Unit un;
     while (next_unit<MODE>(wk, row_ptr, active, n_active, n_tiles, iter, un)) {
@@ -166,12 +217,8 @@ __global__ __launch_bounds__(64) void k_ndft_valu(const int32_t* __restrict__ ro
             const int ne = (un.end - c0) < 64 ? (un.end - c0) : 64;
             for (int k = 0; k < ne; ++k) {
                 const EvStage s = st[k];
-                const double x = (double)lane * (double)s.D + (double)s.A;
-                const uint32_t r = mod_q_small(x, Qd, g.invQ);
-                double rv = (double)r * g.invQ;
-                if (rv >= 0.5) rv -= 1.0;
                 float c, sn;
-                cis_rev((float)rv, c, sn);
+                sincos_fixed(frac_phase(s.phiA, s.q1lo, s.q1hi, s.q2, (uint32_t)lane), sn, c);
                 float zr = s.a * c, zi = s.a * sn;
 #pragma unroll
                 for (int m = 0; m < BPL; ++m) {
@@ -216,17 +263,18 @@ __global__ __launch_bounds__(64) void k_ndft_valu(const int32_t* __restrict__ ro
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 
 template <int NB, int MODE>
-__global__ __launch_bounds__(64) void k_ndft_mfma(const int32_t* __restrict__ row_ptr,
-                                                  const uint32_t* __restrict__ t_rel,
-                                                  const float* __restrict__ av,
-                                                  const int32_t* __restrict__ active,
-                                                  int32_t n_active, GridDev g, int n_wtiles,
-                                                  float* __restrict__ power, WorkDev wk) {
+__global__ __launch_bounds__(64, 2) void k_ndft_mfma(const int32_t* __restrict__ row_ptr,
+                                                     const uint32_t* __restrict__ t_rel,
+                                                     const float* __restrict__ av,
+                                                     const int32_t* __restrict__ active,
+                                                     int32_t n_active, GridDev g, int n_wtiles,
+                                                     float* __restrict__ power, WorkDev wk) {
     __shared__ EvStage st[64];
     const int lane = threadIdx.x;
-    const double Qd = (double)g.Q;
     const int r32 = lane & 31;
     const bool upper = lane >= 32;
+    // lower lanes form U(row r32) = a exp(i 2 pi (A + 32 r32 D)/Q); upper lanes V(col r32)
+    const uint32_t m = upper ? (uint32_t)r32 : 32u * (uint32_t)r32;
     int64_t iter = 0;
     Unit un;
     while (next_unit<MODE>(wk, row_ptr, active, n_active, n_wtiles, iter, un)) {
@@ -244,33 +292,27 @@ __global__ __launch_bounds__(64) void k_ndft_mfma(const int32_t* __restrict__ ro
             const int ne = (un.end - c0) < 64 ? (un.end - c0) : 64;
             for (int k = 0; k < ne; ++k) {
                 const EvStage s = st[k];
-                const double D = (double)s.D;
-                // column phasor V(s = r32)
-                const uint32_t rv = mod_q_small((double)r32 * D, Qd, g.invQ);
-                double fv = (double)rv * g.invQ;
-                if (fv >= 0.5) fv -= 1.0;
-                float vc, vs;
-                cis_rev((float)fv, vc, vs);
-                // row phasor U(b = r32) of the first 32-row tile
-                const uint32_t ru = mod_q_small((double)s.A + 32.0 * (double)r32 * D, Qd, g.invQ);
-                double fu = (double)ru * g.invQ;
-                if (fu >= 0.5) fu -= 1.0;
-                float uc, us;
-                cis_rev((float)fu, uc, us);
-                uc *= s.a;
-                us *= s.a;
-                const float bre = upper ? -vs : vc;
-                const float bim = upper ? vc : vs;
+                float sn, cs;
+                sincos_fixed(frac_phase(upper ? 0u : s.phiA, s.q1lo, s.q1hi, s.q2, m), sn, cs);
+                const float w = upper ? 1.0f : s.a;
+                float uc = cs * w, us = sn * w;            // lower: U; upper: V
+                const float x1 = __shfl_xor(upper ? uc : us, 32, 64);  // lower gets Re V, upper Im U
+                const float x2 = __shfl_xor(us, 32, 64);                // lower gets Im V
+                float aop = upper ? x1 : uc;
+                const float bre = upper ? -us : x1;
+                const float bim = upper ? uc : x2;
 #pragma unroll
                 for (int b = 0; b < NB; ++b) {
-                    const float aop = upper ? us : uc;
                     cre[b] = __builtin_amdgcn_mfma_f32_32x32x2f32(aop, bre, cre[b], 0, 0, 0);
                     cim[b] = __builtin_amdgcn_mfma_f32_32x32x2f32(aop, bim, cim[b], 0, 0, 0);
                     if (b + 1 < NB) {
+                        // next 32-row tile of U: multiply by the exact step phasor
                         const float nr = uc * s.wc - us * s.ws;
                         const float ni = uc * s.ws + us * s.wc;
                         uc = nr;
                         us = ni;
+                        const float xu = __shfl_xor(us, 32, 64);
+                        aop = upper ? xu : uc;
                     }
                 }
             }

@@ -162,6 +162,27 @@ def ddhf_ndft_power(row_ptr, t_rel, a, active, n_active, n_events, grid: Grid, p
     _check(rc, "ddhf_ndft_power")
 
 
+def ddhf_autotune_workspace_size(n_active, n_events, grid: Grid) -> int:
+    b = C.c_size_t(0)
+    _check(lib().ddhf_autotune_workspace_size(C.c_int32(n_active), C.c_int64(n_events),
+                                              C.byref(grid), C.byref(b)), "workspace_size")
+    return b.value
+
+
+def ddhf_autotune(row_ptr, t_rel, a, active, n_active, n_events, grid: Grid, power, ws,
+                  cache_path: Optional[str] = None, stream=None):
+    """Returns (Launch, best_ms); best_ms is -1 on a cache hit."""
+    out = Launch()
+    ms = C.c_float(0.0)
+    rc = lib().ddhf_autotune(_p(row_ptr), _p(t_rel), _p(a), _p(active), C.c_int32(n_active),
+                             C.c_int64(n_events), C.byref(grid), _p(power), _p(ws),
+                             C.c_size_t(ws.numel()),
+                             cache_path.encode() if cache_path else None, C.byref(out),
+                             C.byref(ms), _stream(stream))
+    _check(rc, "ddhf_autotune")
+    return out, ms.value
+
+
 def ddhf_comb_score(power, n_active, grid: Grid, prm: Params, sf, snr_best, bin_best,
                     snr_all=None, stream=None):
     rc = lib().ddhf_comb_score(_p(power), C.c_int32(n_active), C.byref(grid), C.byref(prm),
@@ -209,42 +230,35 @@ class Window:
 
     def __init__(self, x, y, p, t, W, H, t0, T_w, grid, params, w=None, device="cuda",
                  time_sorted=True, launch: Optional[Launch] = None, order_by_cost=False,
-                 max_boxes=256):
+                 max_boxes=256, capacity: Optional[int] = None):
+        import numpy as np
+
         dev = torch.device(device)
         self.dev = dev
         self.n = int(t.shape[0])
+        self.capacity = max(int(capacity) if capacity is not None else self.n, self.n)
         self.W, self.H, self.t0, self.T_w = int(W), int(H), int(t0), int(T_w)
         self.grid = make_grid(grid)
         self.prm = make_params(params)
         self.launch = launch
         self.order_by_cost = int(order_by_cost)
         self.flags = DDHF_INDEX_TIME_SORTED if time_sorted else 0
-        import numpy as np
-
-        def as_t(v, np_dt, view_dt=None):
-            arr = np.ascontiguousarray(np.asarray(v).astype(np_dt))
-            if view_dt is not None:
-                arr = arr.view(view_dt)
-            if arr.size == 0:
-                arr = np.zeros(1, dtype=arr.dtype)
-            return torch.from_numpy(arr).to(dev)
-
-        n1 = max(self.n, 1)
-        # u16 coordinates travel as int16 tensors with identical bits
-        self.x = as_t(x, np.uint16, np.int16)
-        self.y = as_t(y, np.uint16, np.int16)
-        self.p = as_t(p, np.int8)
-        self.t = as_t(t, np.int64)
-        self.w = None if w is None else as_t(w, np.float32)
+        cap = max(self.capacity, 1)
+        self.x = torch.empty(cap, dtype=torch.int16, device=dev)
+        self.y = torch.empty(cap, dtype=torch.int16, device=dev)
+        self.p = torch.empty(cap, dtype=torch.int8, device=dev)
+        self.t = torch.empty(cap, dtype=torch.int64, device=dev)
+        self.w = None if w is None else torch.empty(cap, dtype=torch.float32, device=dev)
+        self._load(x, y, p, t, w)
         npix = self.W * self.H
         self.npix = npix
         self.row_ptr = torch.empty(npix + 1, dtype=torch.int32, device=dev)
-        self.t_rel = torch.empty(n1, dtype=torch.int32, device=dev)
-        self.a = torch.empty(n1, dtype=torch.float32, device=dev)
-        self.perm = torch.empty(n1, dtype=torch.int32, device=dev)
+        self.t_rel = torch.empty(cap, dtype=torch.int32, device=dev)
+        self.a = torch.empty(cap, dtype=torch.float32, device=dev)
+        self.perm = torch.empty(cap, dtype=torch.int32, device=dev)
         self.counters = torch.zeros(6, dtype=torch.int64, device=dev)
-        self.ws_index = workspace(ddhf_build_pixel_index_workspace_size(self.n, self.W, self.H,
-                                                                        self.T_w, self.flags), dev)
+        self.ws_index = workspace(ddhf_build_pixel_index_workspace_size(
+            self.capacity, self.W, self.H, self.T_w, self.flags), dev)
         self.active = torch.empty(max(npix, 1), dtype=torch.int32, device=dev)
         self.n_active_dev = torch.zeros(1, dtype=torch.int32, device=dev)
         self.ws_active = workspace(ddhf_active_pixels_workspace_size(npix), dev)
@@ -256,6 +270,30 @@ class Window:
         self.n_boxes = torch.zeros(2, dtype=torch.int32, device=dev)
         self.power = None
         self.n_active = None
+
+    def _load(self, x, y, p, t, w=None):
+        """Copies host events into the device buffers (u16 coordinates travel as
+        int16 with identical bits)."""
+        import numpy as np
+        n = int(t.shape[0])
+        if n > self.capacity:
+            raise ValueError(f"{n} events exceed the window capacity {self.capacity}")
+        self.n = n
+        if n == 0:
+            return
+        src = [(self.x, np.ascontiguousarray(x, np.uint16).view(np.int16)),
+               (self.y, np.ascontiguousarray(y, np.uint16).view(np.int16)),
+               (self.p, np.ascontiguousarray(p, np.int8)),
+               (self.t, np.ascontiguousarray(t, np.int64))]
+        if w is not None:
+            src.append((self.w, np.ascontiguousarray(w, np.float32)))
+        for dst, arr in src:
+            dst[:n].copy_(torch.from_numpy(arr), non_blocking=False)
+
+    def reload(self, x, y, p, t, t0):
+        """Replaces the window's events (same sensor, grid and capacity)."""
+        self._load(x, y, p, t)
+        self.t0 = int(t0)
 
     # stage 1 + 2
     def index(self, stream=None):
@@ -279,6 +317,16 @@ class Window:
             self.bin = torch.empty(max(na, 1), dtype=torch.int32, device=self.dev)
             self.ws_ndft = workspace(ddhf_ndft_workspace_size(max(na, 1), self.n, self.grid,
                                                               self.launch), self.dev)
+
+    def autotune(self, cache_path: Optional[str] = None, stream=None):
+        """Times the candidate NDFT launches on this window and keeps the best."""
+        ws = workspace(ddhf_autotune_workspace_size(self.n_active, self.n, self.grid), self.dev)
+        launch, ms = ddhf_autotune(self.row_ptr, self.t_rel, self.a, self.active, self.n_active,
+                                   self.n, self.grid, self.power, ws, cache_path, stream)
+        self.launch = launch
+        self.ws_ndft = workspace(ddhf_ndft_workspace_size(max(self.n_active, 1), self.n,
+                                                          self.grid, launch), self.dev)
+        return launch, ms
 
     def spectra(self, stream=None):
         ddhf_ndft_power(self.row_ptr, self.t_rel, self.a, self.active, self.n_active, self.n,

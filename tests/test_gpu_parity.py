@@ -436,3 +436,31 @@ def test_ndft_large_sampled(form):
     err = power_err(P[order][rows], P64, rp, r["active"][rows], r["a"])
     banner(f"  sampled rows {rows.size} max err {err:.3e}")
     assert err <= TOL_P
+
+
+# ---------------------------------------------------------------------------
+# 7. autotuner
+# ---------------------------------------------------------------------------
+
+def test_autotune_picks_a_valid_launch_and_caches(tmp_path):
+    win = synth.medium_window(2)
+    banner("autotune")
+    g = D.window_from_synth(win, device=DEV, order_by_cost=True)
+    g.index()
+    g.fetch_n_active()
+    g.alloc_spectra()
+    cache = str(tmp_path / "tune.jsonl")
+    launch, ms = g.autotune(cache)
+    assert ms > 0 and launch.kernel in (0, 1)
+    # a second call hits the cache and returns the same launch
+    launch2, ms2 = g.autotune(cache)
+    assert ms2 == -1.0
+    assert (launch2.kernel, launch2.bins_per_lane, launch2.split_events, launch2.persistent) == \
+           (launch.kernel, launch.bins_per_lane, launch.split_events, launch.persistent)
+    # the chosen launch is deterministic
+    g.spectra()
+    torch.cuda.synchronize()
+    P1 = to_np(g.power, g.n_active * win.grid.K).copy()
+    g.spectra()
+    torch.cuda.synchronize()
+    assert np.array_equal(P1, to_np(g.power, g.n_active * win.grid.K))
