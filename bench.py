@@ -55,7 +55,72 @@ def parse():
                     help="target CPU time of the oracle baseline sample (0 = skip)")
     ap.add_argument("--stream-steps", type=int, default=400, help="timed stream steps (0 = skip)")
     ap.add_argument("--plain-frames", type=int, default=15, help="plain recompute frames timed")
+    ap.add_argument("--autotune-cache", default=None,
+                    help="JSON-lines autotuner cache: read the launch from it, or time the "
+                         "candidates and append the winner (default: always time)")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain device copy of COPY_BYTES (the known-size kernel "
+                         "that FETCH_SIZE / WRITE_SIZE are scaled by) and exit")
+    ap.add_argument("--traffic-summary", nargs=4,
+                    metavar=("FETCH_CSV", "WRITE_CSV", "CAL_FETCH_CSV", "CAL_WRITE_CSV"),
+                    help="write profiles/traffic_<kernel>_<workload>.json from rocprofv3 --pmc "
+                         "counter CSVs of this bench (--kernel valu|mfma) and of "
+                         "--copy-calibration, then exit")
     return ap.parse_args()
+
+
+COPY_BYTES = 256 << 20
+
+
+def copy_calibration():
+    import torch
+    a = torch.ones(COPY_BYTES // 4, dtype=torch.float32, device="cuda:0")
+    b = torch.empty_like(a)
+    torch.cuda.synchronize()
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes": COPY_BYTES, "launches": 3}), flush=True)
+
+
+def _pmc_mean_kib(path, counter, name_part):
+    """Mean per-dispatch value of one counter over the dispatches whose kernel
+    name contains name_part (rocprofv3 counter_collection.csv)."""
+    import csv
+    vals = []
+    with open(path) as f:
+        for r in csv.DictReader(f):
+            if r["Counter_Name"] == counter and name_part in r["Kernel_Name"]:
+                vals.append(float(r["Counter_Value"]))
+    if not vals:
+        raise SystemExit(f"no {counter} rows for kernels named *{name_part}* in {path}")
+    return sum(vals) / len(vals), len(vals)
+
+
+def traffic_summary(args, fetch_csv, write_csv, cal_fetch_csv, cal_write_csv):
+    """HBM bytes per NDFT launch: FETCH_SIZE and WRITE_SIZE (KiB per dispatch),
+    each scaled by bytes / reading of the plain copy kernel."""
+    if args.kernel not in ("valu", "mfma"):
+        raise SystemExit("--traffic-summary needs --kernel valu or mfma")
+    name = f"k_ndft_{args.kernel}"
+    cf, _ = _pmc_mean_kib(cal_fetch_csv, "FETCH_SIZE", "copyBuffer")
+    cw, _ = _pmc_mean_kib(cal_write_csv, "WRITE_SIZE", "copyBuffer")
+    fetch_scale = COPY_BYTES / (cf * 1024.0)
+    write_scale = COPY_BYTES / (cw * 1024.0)
+    f, nf = _pmc_mean_kib(fetch_csv, "FETCH_SIZE", name)
+    w, nw = _pmc_mean_kib(write_csv, "WRITE_SIZE", name)
+    rec = {"kernel": name, "workload": args.workload,
+           "source_digest": kernel_source_digest(["ndft.hip", "ddhf_internal.h"]),
+           "fetch_kib_per_dispatch": f, "write_kib_per_dispatch": w, "dispatches": [nf, nw],
+           "copy_fetch_kib": cf, "copy_write_kib": cw,
+           "fetch_scale": fetch_scale, "write_scale": write_scale,
+           "bytes_per_launch": f * 1024.0 * fetch_scale + w * 1024.0 * write_scale}
+    tag = f"ndft_{args.kernel}_{args.workload}"
+    out = os.path.join(ROOT, "profiles", f"traffic_{tag}.json")
+    with open(out, "w") as fo:
+        json.dump(rec, fo, indent=1)
+        fo.write("\n")
+    print(json.dumps(rec), flush=True)
 
 
 def kernel_source_digest(names):
@@ -117,7 +182,7 @@ def stream_leg(args, D, synth, launch):
     packets = [gen.next_packet() for _ in range(n_steps * per_step)]
     st = Stream(W, H, T_w, gen.t_origin, grid, prm,
                 launch=D.make_launch(launch.kernel, launch.bins_per_lane),
-                ring_cap=64, max_step_events=32768, max_touched=32768, max_boxes=256)
+                ring_cap=256, max_step_events=32768, max_touched=32768, max_boxes=256)
     lat, boxes_seen = [], 0
     t_loop0 = None
     for s in range(n_steps):
@@ -179,6 +244,9 @@ def stream_leg(args, D, synth, launch):
 
 def main():
     args = parse()
+    if args.traffic_summary:
+        traffic_summary(args, *args.traffic_summary)
+        return
     if args.gpus != 1:
         print(json.dumps({"error": "this build measures one GPU; multi-GPU runs are not part "
                                    "of it (see DESIGN.md: how the path would shard)"}))
@@ -188,6 +256,9 @@ def main():
     from paper_2603_08386_amd import synth
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
+    if args.copy_calibration:
+        copy_calibration()
+        return
     t_gen = time.time()
     win = getattr(synth, WORKLOADS[args.workload])()
     print(f"[bench] workload {args.workload}: {win.n} events, generated in "
@@ -209,7 +280,7 @@ def main():
         g.fetch_n_active()
         g.alloc_spectra()
         t0 = time.perf_counter()
-        launch, best_ms = g.autotune()
+        launch, best_ms = g.autotune(cache_path=args.autotune_cache)
         tune = {"launch": [launch.kernel, launch.bins_per_lane, launch.split_events,
                            launch.persistent], "best_ms": best_ms,
                 "seconds": time.perf_counter() - t0}

@@ -329,42 +329,56 @@ __global__ __launch_bounds__(kCombThreads) void k_comb(const float* __restrict__
 }
 
 // ---------------------------------------------------------------------------
-// Fast path (K <= 4095, band <= 254).  The row is held in registers across
-// phases.  The band of ranks is found by a two-level radix select on the top
-// 22 bits of the FP32 bit patterns (11 + 11 bits, 2048-bucket histograms);
-// the few values sharing the band's 22-bit keys are ranked exactly by
-// (value, bin).  The spectrum array is then overwritten in place by the
-// window maxima max(P[k - dk .. k + dk]), and one u32 per bin packs the
-// exclusive prefix counts of below-band bins (bits 0-11) and in-band bins
-// (bits 12-19) with the bin's own band index (bits 24-31, 0xFF outside).  A
-// candidate reads three words per harmonic window; window bins inside the
-// band are gathered into registers and the complement median's rank is fixed
-// there.
+// Fast path (K <= 4096, band <= 253 ranks).  One 256-thread workgroup per
+// pixel, 16 bins per thread.
+//   1. Load (coalesced), sum, and a two-level 11-bit radix select on the top
+//      22 bits of the FP32 bit patterns (monotone for P >= 0) that finds the
+//      22-bit keys of ranks b_lo and b_hi; the few values sharing those keys
+//      are ranked exactly by (value, bin).  Flatness (Eq. 7) rides along.
+//   2. Every bin gets a code: band index of its rank, or below / above.
+//   3. For every possible window centre c, one pass over the thread's own
+//      contiguous 16-bin segment (plus halo) stores the window maximum
+//      max P[c - dk .. c + dk] in place of P[c], and packs into the code word
+//      the window's number of below-band bins and of in-band bins.
+//   4. A candidate whose harmonic windows do not overlap reads two words per
+//      harmonic; only windows holding in-band bins are opened to collect their
+//      band indices, and the complement median's band index q is the smallest
+//      solution of q = t + #(window band indices <= q).  Overlapping windows
+//      (small i when f0 / df <= dk) take the general scan.
+// LDS arrays indexed by bin use one padding word per 16 bins and histograms
+// one per 8 buckets, so the per-thread segment walks are free of bank
+// conflicts.
 // ---------------------------------------------------------------------------
-constexpr int kFastItems = 16;    // bins per thread: K <= 4096
+constexpr int kFastItems = 16;     // bins per thread: K <= 4096
 constexpr int kListCap = 1024;
-constexpr int kInbCap = 8;        // in-band window bins kept in registers per candidate
+constexpr int kInbCap = 8;         // in-band window bins kept in registers per candidate
+constexpr int kHistWords = 2048 + 256;
+constexpr uint32_t kCodeCand = 0xFDu, kCodeBelow = 0xFEu, kCodeAbove = 0xFFu;
+
+__device__ __forceinline__ int pad16(int k) { return k + (k >> 4); }
+__device__ __forceinline__ int pad8(int b) { return b + (b >> 3); }
 
 struct Loc {
     int d;
     uint32_t before;
 };
 
-// 2048-bucket histogram, 8 buckets per thread: the bucket holding rank tgt
-// (counting `base` elements before the histogram); only one thread writes.
+// 2048-bucket padded histogram, 8 buckets per thread: the bucket holding rank
+// tgt (counting `base` elements before the histogram); one thread writes out.
 __device__ __forceinline__ void locate2048(const uint32_t* h, uint32_t base, int32_t tgt, Loc* out,
                                            uint32_t* scr) {
     const int tid = threadIdx.x;
     uint32_t c[8];
     uint32_t s = 0;
 #pragma unroll
-    for (int i = 0; i < 8; ++i) { c[i] = h[tid * 8 + i]; s += c[i]; }
+    for (int i = 0; i < 8; ++i) { c[i] = h[tid * 9 + i]; s += c[i]; }
     const uint32_t incl = wave_incl_scan(s);
     const int w = tid / kWave;
     if (__lane_id() == kWave - 1) scr[w] = incl;
     __syncthreads();
     uint32_t run = base + incl - s;
-    for (int k = 0; k < w; ++k) run += scr[k];
+#pragma unroll
+    for (int k = 0; k < kCombThreads / kWave - 1; ++k) run += k < w ? scr[k] : 0u;
 #pragma unroll
     for (int i = 0; i < 8; ++i) {
         if ((int64_t)run <= tgt && tgt < (int64_t)(run + c[i])) {
@@ -386,8 +400,8 @@ __global__ __launch_bounds__(kCombThreads) void k_comb_fast(const float* __restr
                                                             float* __restrict__ snr_all,
                                                             const int32_t* __restrict__ n_dev) {
     extern __shared__ __align__(16) char smem[];
-    float* sP = (float*)smem;                       // [kpad]: spectrum, then window maxima
-    uint32_t* sW = (uint32_t*)(sP + ca.kpad);       // [max(kpad + 4, 4096)]: hists, then codes
+    float* sP = (float*)smem;                 // [pad16(K)]: spectrum, then window maxima
+    uint32_t* sW = (uint32_t*)(sP + ca.kpad); // [2 kHistWords]: histograms, then codes
     __shared__ float sBand[256];
     __shared__ uint16_t sList[kListCap];
     __shared__ double red[kCombThreads / kWave];
@@ -405,9 +419,9 @@ __global__ __launch_bounds__(kCombThreads) void k_comb_fast(const float* __restr
     if (u >= n_active || (n_dev && u >= *n_dev)) return;
     const float* row = power + (int64_t)u * K;
     uint32_t* hA = sW;
-    uint32_t* hB = sW + 2048;
+    uint32_t* hB = sW + kHistWords;
 
-    // ---- P1: load (all loads in flight), sum, first digit (bits 20..30) ---
+    // ---- load (all loads in flight), sum, first digit (bits 20..30) --------
     float v[kFastItems];
 #pragma unroll
     for (int i = 0; i < kFastItems; ++i) {
@@ -415,32 +429,32 @@ __global__ __launch_bounds__(kCombThreads) void k_comb_fast(const float* __restr
         v[i] = k < K ? row[k] : 0.0f;
     }
 #pragma unroll
-    for (int i = 0; i < 8; ++i) hA[tid * 8 + i] = 0u;
+    for (int i = 0; i < 2 * kHistWords / kCombThreads; ++i) sW[tid + i * kCombThreads] = 0u;
     if (tid == 0) {
         l1lo = l1hi = l2lo = l2hi = Loc{0, 0};
         s_nlist = 0;
     }
     __syncthreads();
-    double sum = 0.0;
+    float fsum = 0.0f;  // 16 terms per thread; the block sum is in FP64
 #pragma unroll
     for (int i = 0; i < kFastItems; ++i) {
         const int k = tid + i * kCombThreads;
         if (k < K) {
-            sP[k] = v[i];
-            sum += (double)v[i];
-            atomicAdd(&hA[(__float_as_uint(v[i]) >> 20) & 0x7FFu], 1u);
+            sP[pad16(k)] = v[i];
+            fsum += v[i];
+            atomicAdd(&hA[pad8((int)((__float_as_uint(v[i]) >> 20) & 0x7FFu))], 1u);
         }
     }
-    sum = block_sum_d(sum, red);
+    const double sum = block_sum_d((double)fsum, red);
     const double mean = sum / (double)K;
     const float floor_v = (float)(ca.eps * mean);
     locate2048(hA, 0, ca.b_lo, &l1lo, scr);
     locate2048(hA, 0, ca.b_hi, &l1hi, scr);
     const uint32_t d1lo = (uint32_t)l1lo.d, d1hi = (uint32_t)l1hi.d;
 #pragma unroll
-    for (int i = 0; i < 8; ++i) { hA[tid * 8 + i] = 0u; hB[tid * 8 + i] = 0u; }
+    for (int i = 0; i < 2 * kHistWords / kCombThreads; ++i) sW[tid + i * kCombThreads] = 0u;
     __syncthreads();
-    // ---- P2: log-sum (Eq. 7) and second digit (bits 9..19) ------------------
+    // ---- log-sum (Eq. 7) and second digit (bits 9..19) ----------------------
     double sl = 0.0;
 #pragma unroll
     for (int i = 0; i < kFastItems; ++i) {
@@ -449,8 +463,9 @@ __global__ __launch_bounds__(kCombThreads) void k_comb_fast(const float* __restr
             sl += (double)__log2f(v[i] > floor_v ? v[i] : floor_v);
             const uint32_t b = __float_as_uint(v[i]);
             const uint32_t d1 = (b >> 20) & 0x7FFu;
-            if (d1 == d1lo) atomicAdd(&hA[(b >> 9) & 0x7FFu], 1u);
-            if (d1 == d1hi) atomicAdd(&hB[(b >> 9) & 0x7FFu], 1u);
+            const int d2 = pad8((int)((b >> 9) & 0x7FFu));
+            if (d1 == d1lo) atomicAdd(&hA[d2], 1u);
+            if (d1 == d1hi) atomicAdd(&hB[d2], 1u);
         }
     }
     sl = block_sum_d(sl, red);
@@ -460,37 +475,39 @@ __global__ __launch_bounds__(kCombThreads) void k_comb_fast(const float* __restr
     const uint32_t key_lo = (d1lo << 11) | (uint32_t)l2lo.d;
     const uint32_t key_hi = (d1hi << 11) | (uint32_t)l2hi.d;
     const uint32_t below_base = l2lo.before;  // values with a 22-bit key below key_lo
-    // ---- P3: classify (temporary codes: 0 below, 1 above, 2 candidate) -----
+    // ---- classify: below / above / candidate (histograms are dead now) ------
 #pragma unroll
     for (int i = 0; i < kFastItems; ++i) {
         const int k = tid + i * kCombThreads;
         if (k < K) {
             const uint32_t kk = (__float_as_uint(v[i]) >> 9) & 0x3FFFFFu;
-            const uint32_t code = kk < key_lo ? 0u : (kk > key_hi ? 1u : 2u);
-            if (code == 2u) {
+            const uint32_t code = kk < key_lo ? kCodeBelow : (kk > key_hi ? kCodeAbove : kCodeCand);
+            if (code == kCodeCand) {
                 const uint32_t pos = atomicAdd(&s_nlist, 1u);
                 if (pos < kListCap) sList[pos] = (uint16_t)k;
             }
-            sW[k] = code;
+            sW[pad16(k)] = code;
         }
     }
     __syncthreads();
-    // ---- P4: exact ranks of the candidates (value, bin) -------------------
+    // ---- exact ranks of the candidates by (value, bin) ----------------------
     const int nL = (int)s_nlist;
     if (nL <= kListCap) {
         for (int a = tid; a < nL; a += kCombThreads) {
             const int ki = sList[a];
-            const float vi = sP[ki];
+            const float vi = sP[pad16(ki)];
             uint32_t r = 0;
             for (int b = 0; b < nL; ++b) {
                 const int kj = sList[b];
-                const float vj = sP[kj];
+                const float vj = sP[pad16(kj)];
                 r += (vj < vi || (vj == vi && kj < ki)) ? 1u : 0u;
             }
             const int full = (int)(below_base + r);
-            if (full < ca.b_lo) sW[ki] = 0u;
-            else if (full > ca.b_hi) sW[ki] = 1u;
-            else { sW[ki] = 0x100u + (uint32_t)(full - ca.b_lo); sBand[full - ca.b_lo] = vi; }
+            uint32_t code;
+            if (full < ca.b_lo) code = kCodeBelow;
+            else if (full > ca.b_hi) code = kCodeAbove;
+            else { code = (uint32_t)(full - ca.b_lo); sBand[full - ca.b_lo] = vi; }
+            sW[pad16(ki)] = code;
         }
     } else {
         // many exact ties: rank each candidate bin against all candidate bins
@@ -503,60 +520,91 @@ __global__ __launch_bounds__(kCombThreads) void k_comb_fast(const float* __restr
             const float vi = v[i];
             uint32_t r = 0;
             for (int kj = 0; kj < K; ++kj) {
-                const float vj = sP[kj];
+                const float vj = sP[pad16(kj)];
                 const uint32_t kk = (__float_as_uint(vj) >> 9) & 0x3FFFFFu;
                 if (kk >= key_lo && kk <= key_hi && (vj < vi || (vj == vi && kj < ki))) ++r;
             }
             const int full = (int)(below_base + r);
             uint32_t code;
-            if (full < ca.b_lo) code = 0u;
-            else if (full > ca.b_hi) code = 1u;
-            else { code = 0x100u + (uint32_t)(full - ca.b_lo); sBand[full - ca.b_lo] = vi; }
-            sW[ki] = code;
+            if (full < ca.b_lo) code = kCodeBelow;
+            else if (full > ca.b_hi) code = kCodeAbove;
+            else { code = (uint32_t)(full - ca.b_lo); sBand[full - ca.b_lo] = vi; }
+            sW[pad16(ki)] = code;
         }
     }
     __syncthreads();
-    // ---- P5: window maxima in place; packed prefix counts -----------------
+    // ---- per-centre window maxima and window counts --------------------------
+    // Per bin e = [below] | [in band] << 6 | (band index + 1) << 12 for in-band
+    // bins; a window's sum of e holds its below count (bits 0-5), in-band count
+    // (bits 6-11) and, when exactly one bin is in band, that bin's band index
+    // + 1 (bits 12 and up).  The code word becomes own code | sum << 8, and the
+    // spectrum array the window maxima (windows leaving [0, K) are never read).
     {
-        const int seg = (K + kCombThreads - 1) / kCombThreads;  // <= 16
-        const int k0 = tid * seg;
+        const int k0 = tid * kFastItems;
         float wm[kFastItems];
-        uint32_t code[kFastItems];
-        uint32_t s = 0;
+        uint32_t wc[kFastItems];
+        if (DKT >= 0) {
+            constexpr int D = DKT >= 0 ? DKT : 0;
+            constexpr int NH = kFastItems + 2 * D;
+            float hv[NH];
+            uint32_t cum[NH], own[kFastItems];
+            uint32_t run = 0;
+#pragma unroll
+            for (int q = 0; q < NH; ++q) {
+                const int k = k0 - D + q;
+                const bool in = k >= 0 && k < K;
+                hv[q] = in ? sP[pad16(k)] : 0.0f;
+                const uint32_t c = in ? (sW[pad16(k)] & 0xFFu) : kCodeAbove;
+                if (q >= D && q < D + kFastItems) own[q - D] = c;
+                run += c == kCodeBelow ? 1u : (c < kCodeCand ? (0x40u | ((c + 1u) << 12)) : 0u);
+                cum[q] = run;
+            }
+#pragma unroll
+            for (int j = 0; j < kFastItems; ++j) {
+                float mx = hv[j];
+#pragma unroll
+                for (int q = 1; q <= 2 * D; ++q) mx = fmaxf(mx, hv[j + q]);
+                const uint32_t sum = cum[j + 2 * D] - (j > 0 ? cum[j - 1] : 0u);
+                wm[j] = mx;
+                wc[j] = own[j] | (sum << 8);
+            }
+        } else {
+#pragma unroll
+            for (int j = 0; j < kFastItems; ++j) {
+                const int k = k0 + j;
+                float mx = 0.0f;
+                uint32_t sum = 0, own = kCodeAbove;
+                if (k < K) {
+                    own = sW[pad16(k)] & 0xFFu;
+                    if (k >= dk && k + dk <= K - 1) {
+                        mx = sP[pad16(k - dk)];
+                        for (int q = -dk; q <= dk; ++q) {
+                            mx = fmaxf(mx, sP[pad16(k + q)]);
+                            const uint32_t c = sW[pad16(k + q)] & 0xFFu;
+                            sum += c == kCodeBelow ? 1u
+                                 : (c < kCodeCand ? (0x40u | ((c + 1u) << 12)) : 0u);
+                        }
+                    }
+                }
+                wm[j] = mx;
+                wc[j] = own | (sum << 8);
+            }
+        }
+        __syncthreads();  // every read of the old arrays is done
 #pragma unroll
         for (int j = 0; j < kFastItems; ++j) {
             const int k = k0 + j;
-            const bool in = j < seg && k < K;
-            code[j] = in ? sW[k] : 1u;
-            s += code[j] == 0u ? 1u : (code[j] >= 0x100u ? 0x1000u : 0u);
-            float mx = 0.0f;
-            if (in && k >= dk && k + dk <= K - 1) {
-                mx = sP[k - dk];
-                for (int q = 1; q <= 2 * dk; ++q) mx = fmaxf(mx, sP[k - dk + q]);
-            }
-            wm[j] = mx;
-        }
-        const uint32_t incl = wave_incl_scan(s);
-        const int w = tid / kWave;
-        if (__lane_id() == kWave - 1) scr[w] = incl;
-        __syncthreads();  // every window read of sP is done before sP is overwritten
-        uint32_t run = incl - s;
-        for (int q = 0; q < w; ++q) run += scr[q];
-#pragma unroll
-        for (int j = 0; j < kFastItems; ++j) {
-            const int k = k0 + j;
-            if (j < seg && k < K) {
-                const uint32_t rk = code[j] >= 0x100u ? (code[j] - 0x100u) : 0xFFu;
-                sW[k] = run | (rk << 24);
-                sP[k] = wm[j];
-                run += code[j] == 0u ? 1u : (code[j] >= 0x100u ? 0x1000u : 0u);
+            if (k < K) {
+                sP[pad16(k)] = wm[j];
+                sW[pad16(k)] = wc[j];
             }
         }
-        if (k0 < K && k0 + seg >= K) sW[K] = run;
     }
     __syncthreads();
-    // ---- P6: candidates (Eq. 8-11) ----------------------------------------
+    // ---- candidates (Eq. 8-11) ----------------------------------------------
+    constexpr int MI = MT > 0 ? MT : kInbCap;  // windows whose in-band bin is kept
     const float fden_floor = (float)(ca.eps * mean);
+    const int bw = ca.b_hi - ca.b_lo;
     float best = 0.0f;
     int best_i = -1;
     for (int i = dk + tid; i <= i_max; i += kCombThreads) {
@@ -566,81 +614,89 @@ __global__ __launch_bounds__(kCombThreads) void k_comb_fast(const float* __restr
             return (int)floor(num / (double)ca.df + 0.5);
         };
         int mv = 0;
+        bool slow = false;  // overlapping windows, or a window with several in-band bins
+        int prev_c = -1;
 #pragma unroll
         for (int m = 1; m <= (MT > 0 ? MT : 32); ++m) {
             if (m > M) break;
-            if (centre(m) + dk > K - 1) break;
+            const int cm = centre(m);
+            if (cm + dk > K - 1) break;
+            if (m > 1 && cm - prev_c <= 2 * dk) slow = true;
+            prev_c = cm;
             mv = m;
         }
         float snr = 0.0f;
         if (mv >= ca.h_min) {
             float smax = 0.0f;
-            int hsize = 0;
-            uint32_t below = 0;
-            int nin = 0;
-            bool spill = false;
-            int inr[kInbCap];
-            int prev_hi = -1;
+            int below = 0;
+            int inr[MI];
+#pragma unroll
+            for (int j = 0; j < MI; ++j) inr[j] = 0x7FFF;
 #pragma unroll
             for (int m = 1; m <= (MT > 0 ? MT : 32); ++m) {
                 if (m > mv) break;
                 const int cm = centre(m);
-                smax += sP[cm];
-                const int lo = (cm - dk) > prev_hi + 1 ? (cm - dk) : prev_hi + 1;
-                const int hi = cm + dk;
-                if (lo <= hi) {
-                    hsize += hi - lo + 1;
-                    const uint32_t d = (sW[hi + 1] & 0xFFFFFu) - (sW[lo] & 0xFFFFFu);
-                    below += d & 0xFFFu;
-                    if (d >> 12) {
-                        for (int k = lo; k <= hi; ++k) {
-                            const uint32_t rk = sW[k] >> 24;
-                            if (rk != 0xFFu) {
-                                if (nin < kInbCap) inr[nin++] = (int)rk;
-                                else spill = true;
-                            }
-                        }
-                    }
-                }
-                prev_hi = hi;
+                smax += sP[pad16(cm)];
+                const uint32_t w = sW[pad16(cm)];
+                below += (int)((w >> 8) & 0x3Fu);
+                const uint32_t wi = (w >> 14) & 0x3Fu;
+                if (wi == 1u && m <= MI) inr[m - 1] = (int)((w >> 20) & 0xFFFu) - 1;
+                else if (wi != 0u) slow = true;
             }
-            const float N = smax / (float)mv;
-            const int nc = K - hsize;
-            float med = 0.0f;
-            if (nc > 0) {
-                const int r = (nc - 1) / 2;
-                // band index of the median: q = r + below + #(in-band window bins <= q)
-                int q = r + (int)below - ca.b_lo;
-                if (!spill) {
-                    for (int iter = 0; iter <= kInbCap; ++iter) {
-                        int extra = 0;
-                        for (int j = 0; j < nin; ++j) extra += inr[j] <= q ? 1 : 0;
-                        const int qn = r + (int)below - ca.b_lo + extra;
-                        if (qn == q) break;
-                        q = qn;
-                    }
-                } else {
-                    const int hmax = M * (2 * dk + 1);
-                    for (int iter = 0; iter <= hmax + 1; ++iter) {
-                        int extra = 0, ph = -1;
-                        for (int m = 1; m <= mv; ++m) {
-                            const int cm = centre(m);
-                            const int lo = (cm - dk) > ph + 1 ? (cm - dk) : ph + 1;
-                            for (int k = lo; k <= cm + dk; ++k) {
-                                const uint32_t rk = sW[k] >> 24;
-                                if (rk != 0xFFu && (int)rk <= q) ++extra;
-                            }
-                            ph = cm + dk;
-                        }
-                        const int qn = r + (int)below - ca.b_lo + extra;
-                        if (qn == q) break;
-                        q = qn;
-                    }
+            int hsize = mv * (2 * dk + 1);
+            int q;
+            if (!slow) {
+                const int r = (K - hsize - 1) / 2;
+                const int t = r + below - ca.b_lo;
+                // band index of the median: smallest q with q = t + #(window band indices <= q)
+                q = t;
+#pragma unroll
+                for (int iter = 0; iter <= MI; ++iter) {
+                    int extra = 0;
+#pragma unroll
+                    for (int j = 0; j < MI; ++j) extra += inr[j] <= q ? 1 : 0;
+                    q = t + extra;
                 }
-                const int bw = ca.b_hi - ca.b_lo;
+            } else {
+                // distinct window bins, scanned with their own codes
+                below = 0;
+                hsize = 0;
+                int ph = -1;
+                for (int m = 1; m <= mv; ++m) {
+                    const int cm = centre(m);
+                    const int lo = (cm - dk) > ph + 1 ? (cm - dk) : ph + 1;
+                    for (int k = lo; k <= cm + dk; ++k) {
+                        ++hsize;
+                        below += (sW[pad16(k)] & 0xFFu) == kCodeBelow ? 1 : 0;
+                    }
+                    ph = cm + dk;
+                }
+                const int r = (K - hsize - 1) / 2;
+                const int t = r + below - ca.b_lo;
+                q = t;
+                const int hmax = M * (2 * dk + 1);
+                for (int iter = 0; iter <= hmax + 1; ++iter) {
+                    int extra = 0;
+                    ph = -1;
+                    for (int m = 1; m <= mv; ++m) {
+                        const int cm = centre(m);
+                        const int lo = (cm - dk) > ph + 1 ? (cm - dk) : ph + 1;
+                        for (int k = lo; k <= cm + dk; ++k) {
+                            const uint32_t c = sW[pad16(k)] & 0xFFu;
+                            if (c < kCodeCand && (int)c <= q) ++extra;
+                        }
+                        ph = cm + dk;
+                    }
+                    if (t + extra == q) break;
+                    q = t + extra;
+                }
+            }
+            float med = 0.0f;
+            if (K - hsize > 0) {
                 q = q < 0 ? 0 : (q > bw ? bw : q);
                 med = sBand[q];
             }
+            const float N = smax / (float)mv;
             const float den = med > fden_floor ? med : fden_floor;
             snr = den > 0.0f ? N / den : 0.0f;
             if (best_i < 0 || snr > best) { best = snr; best_i = i; }
@@ -730,18 +786,19 @@ int comb_run(const float* power, int32_t n_active, const int32_t* n_dev, const d
         if (i_max > ca.K - 1 - ca.dk) i_max = ca.K - 1 - ca.dk;
     }
     const int bw = ca.b_hi - ca.b_lo + 1;
-    if (ca.K <= 4095 && bw <= 254) {
-        const int wwords = (ca.kpad + 4) > 4096 ? (ca.kpad + 4) : 4096;
-        const size_t lds = (size_t)ca.kpad * 4 + (size_t)wwords * 4;
+    if (ca.K <= 4096 && bw <= 253) {
+        CombArgs cf = ca;
+        cf.kpad = ((ca.K - 1) + ((ca.K - 1) >> 4) + 1 + 3) / 4 * 4;  // padded bin array
+        const size_t lds = (size_t)cf.kpad * 4 + (size_t)2 * kHistWords * 4;
         const dim3 gr((unsigned)n_active), bl(kCombThreads);
         if (ca.M == 4 && ca.dk == 3)
-            hipLaunchKernelGGL((k_comb_fast<4, 3>), gr, bl, lds, s, power, n_active, ca, i_max, sf,
+            hipLaunchKernelGGL((k_comb_fast<4, 3>), gr, bl, lds, s, power, n_active, cf, i_max, sf,
                                snr_best, bin_best, snr_all, n_dev);
         else if (ca.M == 5 && ca.dk == 3)
-            hipLaunchKernelGGL((k_comb_fast<5, 3>), gr, bl, lds, s, power, n_active, ca, i_max, sf,
+            hipLaunchKernelGGL((k_comb_fast<5, 3>), gr, bl, lds, s, power, n_active, cf, i_max, sf,
                                snr_best, bin_best, snr_all, n_dev);
         else
-            hipLaunchKernelGGL((k_comb_fast<-1, -1>), gr, bl, lds, s, power, n_active, ca, i_max,
+            hipLaunchKernelGGL((k_comb_fast<-1, -1>), gr, bl, lds, s, power, n_active, cf, i_max,
                                sf, snr_best, bin_best, snr_all, n_dev);
         DDHF_LAUNCH_CHECK();
         return DDHF_OK;

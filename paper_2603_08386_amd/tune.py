@@ -78,23 +78,28 @@ def accuracy(data: List[Labelled], w, tau, beta) -> float:
     return hit / max(count, 1)
 
 
-def tune_gradient(data: List[Labelled], steps: int = 60, lr: float = 0.05, dtype=torch.float32):
+def tune_gradient(data: List[Labelled], steps: int = 60, lr: float = 0.1, dtype=torch.float32):
+    """Adam on scale-free parameters: w = w_raw / nh (w_raw starts at 1) and
+    tau = med + sd * theta (theta starts at 0), so one learning rate suits both
+    whatever the spectra's scale."""
     med, sd = _score_scale(data, dtype)
     beta = 4.0 / sd
     dev = data[0].e.device
     nh = data[0].graph.nh
-    w = torch.full((nh,), 1.0 / nh, dtype=dtype, device=dev, requires_grad=True)
-    tau = torch.tensor([med], dtype=dtype, device=dev, requires_grad=True)
-    opt = torch.optim.Adam([w, tau], lr=lr * max(abs(med), 1e-3))
+    w_raw = torch.ones(nh, dtype=dtype, device=dev, requires_grad=True)
+    theta = torch.zeros(1, dtype=dtype, device=dev, requires_grad=True)
+    opt = torch.optim.Adam([w_raw, theta], lr=lr)
     hist = []
     for _ in range(steps):
         opt.zero_grad()
-        loss = bce_loss(data, w, tau, beta)
+        loss = bce_loss(data, w_raw / nh, med + sd * theta, beta)
         loss.backward()
         opt.step()
         hist.append(float(loss.item()))
-    return dict(w=w.detach(), tau=tau.detach(), beta=beta, loss=hist,
-                accuracy=accuracy(data, w.detach(), tau.detach(), beta))
+    w = (w_raw / nh).detach()
+    tau = (med + sd * theta).detach()
+    hist.append(float(bce_loss(data, w, tau, beta).item()))
+    return dict(w=w, tau=tau, beta=beta, loss=hist, accuracy=accuracy(data, w, tau, beta))
 
 
 def tune_grid(data: List[Labelled], n_tau: int = 41, dtype=torch.float32):

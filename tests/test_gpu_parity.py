@@ -232,7 +232,8 @@ def test_comb_random_spectra_many_shapes():
     for K, M, dk, hmin, f0, df in [(1024, 5, 3, 3, 1000, 1000), (3981, 4, 3, 4, 10_000, 500),
                                    (3991, 4, 3, 4, 10_000, 1000), (777, 6, 2, 2, 750, 500),
                                    (129, 3, 0, 2, 0, 1), (300, 16, 4, 8, 10_000, 500),
-                                   (5000, 4, 3, 4, 10_000, 1000),      # general kernel: K > 4095
+                                   (4096, 4, 3, 4, 10_000, 1000),      # largest fast-path K
+                                   (5000, 4, 3, 4, 10_000, 1000),      # general kernel: K > 4096
                                    (2000, 32, 8, 4, 10_000, 500),      # general kernel: wide band
                                    (600, 4, 6, 3, 10_000, 500)]:       # runtime window width
         grid = Grid(f0=f0, df=df, K=K)
