@@ -330,62 +330,74 @@ __global__ __launch_bounds__(kCombThreads) void k_comb(const float* __restrict__
 
 // ---------------------------------------------------------------------------
 // Fast path (K <= 4096, band <= 253 ranks).  One 256-thread workgroup per
-// pixel, 16 bins per thread.
-//   1. Load (coalesced), sum, and a two-level 11-bit radix select on the top
-//      22 bits of the FP32 bit patterns (monotone for P >= 0) that finds the
-//      22-bit keys of ranks b_lo and b_hi; the few values sharing those keys
-//      are ranked exactly by (value, bin).  Flatness (Eq. 7) rides along.
+// pixel; thread t owns the contiguous bins [16 t, 16 t + 16).
+//   1. The row is loaded coalesced and transposed through LDS.  A two-level
+//      11-bit radix select on the top 22 bits of the FP32 bit patterns
+//      (monotone for P >= 0) finds the 22-bit keys of ranks b_lo and b_hi; the
+//      few values sharing those keys are ranked exactly by (value, bin).
+//      Flatness (Eq. 7) rides along.
 //   2. Every bin gets a code: band index of its rank, or below / above.
-//   3. For every possible window centre c, one pass over the thread's own
-//      contiguous 16-bin segment (plus halo) stores the window maximum
-//      max P[c - dk .. c + dk] in place of P[c], and packs into the code word
-//      the window's number of below-band bins and of in-band bins.
+//   3. For every window centre c, the thread's segment plus a halo of dk bins
+//      gives the window maximum max P[c - dk .. c + dk] (stored in place of
+//      P[c]) and, packed into c's code word, the window's below-band count,
+//      in-band count and, when one bin is in band, its band index.
 //   4. A candidate whose harmonic windows do not overlap reads two words per
-//      harmonic; only windows holding in-band bins are opened to collect their
-//      band indices, and the complement median's band index q is the smallest
-//      solution of q = t + #(window band indices <= q).  Overlapping windows
-//      (small i when f0 / df <= dk) take the general scan.
-// LDS arrays indexed by bin use one padding word per 16 bins and histograms
-// one per 8 buckets, so the per-thread segment walks are free of bank
-// conflicts.
+//      harmonic; the complement median's band index q is the smallest
+//      solution of q = t + #(window band indices <= q).  Overlapping windows,
+//      or windows with several in-band bins, take a scan of the bin codes.
+// LDS arrays indexed by bin carry one padding word per 16 bins and histograms
+// one per 8 buckets, so segment walks and histogram scans are conflict-free.
 // ---------------------------------------------------------------------------
 constexpr int kFastItems = 16;     // bins per thread: K <= 4096
-constexpr int kListCap = 1024;
+constexpr int kListCap = 512;
 constexpr int kInbCap = 8;         // in-band window bins kept in registers per candidate
 constexpr int kHistWords = 2048 + 256;
 constexpr uint32_t kCodeCand = 0xFDu, kCodeBelow = 0xFEu, kCodeAbove = 0xFFu;
 
 __device__ __forceinline__ int pad16(int k) { return k + (k >> 4); }
-__device__ __forceinline__ int pad8(int b) { return b + (b >> 3); }
 
 struct Loc {
     int d;
     uint32_t before;
 };
 
-// 2048-bucket padded histogram, 8 buckets per thread: the bucket holding rank
-// tgt (counting `base` elements before the histogram); one thread writes out.
-__device__ __forceinline__ void locate2048(const uint32_t* h, uint32_t base, int32_t tgt, Loc* out,
-                                           uint32_t* scr) {
+// Bucket of rank tgt in a padded 2048-bucket histogram (8 buckets per thread,
+// `base` elements counted before it); one thread writes `out`.  Two
+// histograms / targets per call share the barriers.
+template <bool SAME>
+__device__ __forceinline__ void locate2048x2(const uint32_t* h1, uint32_t base1, int32_t tgt1,
+                                             Loc* out1, const uint32_t* h2, uint32_t base2,
+                                             int32_t tgt2, Loc* out2, uint32_t* scr) {
     const int tid = threadIdx.x;
-    uint32_t c[8];
-    uint32_t s = 0;
-#pragma unroll
-    for (int i = 0; i < 8; ++i) { c[i] = h[tid * 9 + i]; s += c[i]; }
-    const uint32_t incl = wave_incl_scan(s);
-    const int w = tid / kWave;
-    if (__lane_id() == kWave - 1) scr[w] = incl;
-    __syncthreads();
-    uint32_t run = base + incl - s;
-#pragma unroll
-    for (int k = 0; k < kCombThreads / kWave - 1; ++k) run += k < w ? scr[k] : 0u;
+    uint32_t c1[8], c2[8];
+    uint32_t s1 = 0, s2 = 0;
 #pragma unroll
     for (int i = 0; i < 8; ++i) {
-        if ((int64_t)run <= tgt && tgt < (int64_t)(run + c[i])) {
-            out->d = tid * 8 + i;
-            out->before = run;
-        }
-        run += c[i];
+        c1[i] = h1[tid * 9 + i];
+        c2[i] = SAME ? c1[i] : h2[tid * 9 + i];
+        s1 += c1[i];
+        s2 += c2[i];
+    }
+    const uint32_t i1 = wave_incl_scan(s1);
+    const uint32_t i2 = SAME ? i1 : wave_incl_scan(s2);
+    const int w = tid / kWave;
+    if (__lane_id() == kWave - 1) {
+        scr[w] = i1;
+        scr[kCombThreads / kWave + w] = i2;
+    }
+    __syncthreads();
+    uint32_t r1 = base1 + i1 - s1, r2 = base2 + i2 - s2;
+#pragma unroll
+    for (int k = 0; k < kCombThreads / kWave - 1; ++k) {
+        r1 += k < w ? scr[k] : 0u;
+        r2 += k < w ? scr[kCombThreads / kWave + k] : 0u;
+    }
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+        if ((int64_t)r1 <= tgt1 && tgt1 < (int64_t)(r1 + c1[i])) { out1->d = tid * 8 + i; out1->before = r1; }
+        if ((int64_t)r2 <= tgt2 && tgt2 < (int64_t)(r2 + c2[i])) { out2->d = tid * 8 + i; out2->before = r2; }
+        r1 += c1[i];
+        r2 += c2[i];
     }
     __syncthreads();
 }
@@ -401,11 +413,11 @@ __global__ __launch_bounds__(kCombThreads) void k_comb_fast(const float* __restr
                                                             const int32_t* __restrict__ n_dev) {
     extern __shared__ __align__(16) char smem[];
     float* sP = (float*)smem;                 // [pad16(K)]: spectrum, then window maxima
-    uint32_t* sW = (uint32_t*)(sP + ca.kpad); // [2 kHistWords]: histograms, then codes
+    uint32_t* sW = (uint32_t*)(sP + ca.kpad); // [2 kHistWords]: histograms, then code words
     __shared__ float sBand[256];
     __shared__ uint16_t sList[kListCap];
     __shared__ double red[kCombThreads / kWave];
-    __shared__ uint32_t scr[kCombThreads / kWave];
+    __shared__ uint32_t scr[2 * kCombThreads / kWave];
     __shared__ Loc l1lo, l1hi, l2lo, l2hi;
     __shared__ uint32_t s_nlist;
     __shared__ float s_best[kCombThreads / kWave];
@@ -420,36 +432,49 @@ __global__ __launch_bounds__(kCombThreads) void k_comb_fast(const float* __restr
     const float* row = power + (int64_t)u * K;
     uint32_t* hA = sW;
     uint32_t* hB = sW + kHistWords;
+    const int k0 = tid * kFastItems;       // first bin of this thread's segment
+    const int s0 = tid * (kFastItems + 1); // its padded LDS index
 
-    // ---- load (all loads in flight), sum, first digit (bits 20..30) --------
-    float v[kFastItems];
+    // ---- coalesced load, transpose through LDS ------------------------------
+    {
+        float g[kFastItems];
 #pragma unroll
-    for (int i = 0; i < kFastItems; ++i) {
-        const int k = tid + i * kCombThreads;
-        v[i] = k < K ? row[k] : 0.0f;
-    }
+        for (int i = 0; i < kFastItems; ++i) {
+            const int k = tid + i * kCombThreads;
+            g[i] = k < K ? row[k] : 0.0f;
+        }
 #pragma unroll
-    for (int i = 0; i < 2 * kHistWords / kCombThreads; ++i) sW[tid + i * kCombThreads] = 0u;
-    if (tid == 0) {
-        l1lo = l1hi = l2lo = l2hi = Loc{0, 0};
-        s_nlist = 0;
+        for (int i = 0; i < 2 * kHistWords / kCombThreads; ++i) sW[tid + i * kCombThreads] = 0u;
+        if (tid == 0) {
+            l1lo = l1hi = l2lo = l2hi = Loc{0, 0};
+            s_nlist = 0;
+        }
+        const int ps = pad16(tid);
+#pragma unroll
+        for (int i = 0; i < kFastItems; ++i)
+            if (tid + i * kCombThreads < K) sP[ps + i * (kCombThreads + kCombThreads / 16)] = g[i];
     }
     __syncthreads();
+    float v[kFastItems];
+    int nmine = K - k0;  // bins of this segment inside [0, K)
+    nmine = nmine < 0 ? 0 : (nmine > kFastItems ? kFastItems : nmine);
+#pragma unroll
+    for (int j = 0; j < kFastItems; ++j) v[j] = j < nmine ? sP[s0 + j] : 0.0f;
+
+    // ---- sum and first digit (bits 20..30) ----------------------------------
     float fsum = 0.0f;  // 16 terms per thread; the block sum is in FP64
 #pragma unroll
-    for (int i = 0; i < kFastItems; ++i) {
-        const int k = tid + i * kCombThreads;
-        if (k < K) {
-            sP[pad16(k)] = v[i];
-            fsum += v[i];
-            atomicAdd(&hA[pad8((int)((__float_as_uint(v[i]) >> 20) & 0x7FFu))], 1u);
+    for (int j = 0; j < kFastItems; ++j) {
+        if (j < nmine) {
+            fsum += v[j];
+            const uint32_t d1 = (__float_as_uint(v[j]) >> 20) & 0x7FFu;
+            atomicAdd(&hA[d1 + (d1 >> 3)], 1u);
         }
     }
     const double sum = block_sum_d((double)fsum, red);
     const double mean = sum / (double)K;
     const float floor_v = (float)(ca.eps * mean);
-    locate2048(hA, 0, ca.b_lo, &l1lo, scr);
-    locate2048(hA, 0, ca.b_hi, &l1hi, scr);
+    locate2048x2<true>(hA, 0, ca.b_lo, &l1lo, hA, 0, ca.b_hi, &l1hi, scr);
     const uint32_t d1lo = (uint32_t)l1lo.d, d1hi = (uint32_t)l1hi.d;
 #pragma unroll
     for (int i = 0; i < 2 * kHistWords / kCombThreads; ++i) sW[tid + i * kCombThreads] = 0u;
@@ -457,42 +482,60 @@ __global__ __launch_bounds__(kCombThreads) void k_comb_fast(const float* __restr
     // ---- log-sum (Eq. 7) and second digit (bits 9..19) ----------------------
     double sl = 0.0;
 #pragma unroll
-    for (int i = 0; i < kFastItems; ++i) {
-        const int k = tid + i * kCombThreads;
-        if (k < K) {
-            sl += (double)__log2f(v[i] > floor_v ? v[i] : floor_v);
-            const uint32_t b = __float_as_uint(v[i]);
+    for (int j = 0; j < kFastItems; ++j) {
+        if (j < nmine) {
+            sl += (double)__log2f(v[j] > floor_v ? v[j] : floor_v);
+            const uint32_t b = __float_as_uint(v[j]);
             const uint32_t d1 = (b >> 20) & 0x7FFu;
-            const int d2 = pad8((int)((b >> 9) & 0x7FFu));
-            if (d1 == d1lo) atomicAdd(&hA[d2], 1u);
-            if (d1 == d1hi) atomicAdd(&hB[d2], 1u);
+            const uint32_t d2 = (b >> 9) & 0x7FFu;
+            if (d1 == d1lo) atomicAdd(&hA[d2 + (d2 >> 3)], 1u);
+            if (d1 == d1hi) atomicAdd(&hB[d2 + (d2 >> 3)], 1u);
         }
     }
     sl = block_sum_d(sl, red);
     if (tid == 0) sf_out[u] = mean > 0.0 ? (float)exp2(sl / (double)K - log2(mean)) : 1.0f;
-    locate2048(hA, l1lo.before, ca.b_lo, &l2lo, scr);
-    locate2048(hB, l1hi.before, ca.b_hi, &l2hi, scr);
+    locate2048x2<false>(hA, l1lo.before, ca.b_lo, &l2lo, hB, l1hi.before, ca.b_hi, &l2hi, scr);
     const uint32_t key_lo = (d1lo << 11) | (uint32_t)l2lo.d;
     const uint32_t key_hi = (d1hi << 11) | (uint32_t)l2hi.d;
     const uint32_t below_base = l2lo.before;  // values with a 22-bit key below key_lo
     // ---- classify: below / above / candidate (histograms are dead now) ------
 #pragma unroll
-    for (int i = 0; i < kFastItems; ++i) {
-        const int k = tid + i * kCombThreads;
-        if (k < K) {
-            const uint32_t kk = (__float_as_uint(v[i]) >> 9) & 0x3FFFFFu;
+    for (int j = 0; j < kFastItems; ++j) {
+        if (j < nmine) {
+            const uint32_t kk = (__float_as_uint(v[j]) >> 9) & 0x3FFFFFu;
             const uint32_t code = kk < key_lo ? kCodeBelow : (kk > key_hi ? kCodeAbove : kCodeCand);
             if (code == kCodeCand) {
                 const uint32_t pos = atomicAdd(&s_nlist, 1u);
-                if (pos < kListCap) sList[pos] = (uint16_t)k;
+                if (pos < kListCap) sList[pos] = (uint16_t)(k0 + j);
             }
-            sW[pad16(k)] = code;
+            sW[s0 + j] = code;
         }
     }
     __syncthreads();
     // ---- exact ranks of the candidates by (value, bin) ----------------------
     const int nL = (int)s_nlist;
-    if (nL <= kListCap) {
+    if (nL <= kWave) {
+        // one wavefront: candidate b's (value, bin) broadcast by readlane
+        if (tid < kWave) {
+            const bool mine = tid < nL;
+            const int ki = mine ? (int)sList[tid] : 0;
+            const float vi = mine ? sP[pad16(ki)] : 0.0f;
+            uint32_t r = 0;
+            for (int b = 0; b < nL; ++b) {
+                const float vj = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(vi), b));
+                const int kj = __builtin_amdgcn_readlane(ki, b);
+                r += (vj < vi || (vj == vi && kj < ki)) ? 1u : 0u;
+            }
+            if (mine) {
+                const int full = (int)(below_base + r);
+                uint32_t code;
+                if (full < ca.b_lo) code = kCodeBelow;
+                else if (full > ca.b_hi) code = kCodeAbove;
+                else { code = (uint32_t)(full - ca.b_lo); sBand[full - ca.b_lo] = vi; }
+                sW[pad16(ki)] = code;
+            }
+        }
+    } else if (nL <= kListCap) {
         for (int a = tid; a < nL; a += kCombThreads) {
             const int ki = sList[a];
             const float vi = sP[pad16(ki)];
@@ -512,12 +555,12 @@ __global__ __launch_bounds__(kCombThreads) void k_comb_fast(const float* __restr
     } else {
         // many exact ties: rank each candidate bin against all candidate bins
 #pragma unroll 1
-        for (int i = 0; i < kFastItems; ++i) {
-            const int ki = tid + i * kCombThreads;
-            if (ki >= K) continue;
-            const uint32_t kki = (__float_as_uint(v[i]) >> 9) & 0x3FFFFFu;
+        for (int j = 0; j < kFastItems; ++j) {
+            if (j >= nmine) break;
+            const uint32_t kki = (__float_as_uint(v[j]) >> 9) & 0x3FFFFFu;
             if (kki < key_lo || kki > key_hi) continue;
-            const float vi = v[i];
+            const int ki = k0 + j;
+            const float vi = v[j];
             uint32_t r = 0;
             for (int kj = 0; kj < K; ++kj) {
                 const float vj = sP[pad16(kj)];
@@ -529,7 +572,7 @@ __global__ __launch_bounds__(kCombThreads) void k_comb_fast(const float* __restr
             if (full < ca.b_lo) code = kCodeBelow;
             else if (full > ca.b_hi) code = kCodeAbove;
             else { code = (uint32_t)(full - ca.b_lo); sBand[full - ca.b_lo] = vi; }
-            sW[pad16(ki)] = code;
+            sW[s0 + j] = code;
         }
     }
     __syncthreads();
@@ -540,7 +583,6 @@ __global__ __launch_bounds__(kCombThreads) void k_comb_fast(const float* __restr
     // + 1 (bits 12 and up).  The code word becomes own code | sum << 8, and the
     // spectrum array the window maxima (windows leaving [0, K) are never read).
     {
-        const int k0 = tid * kFastItems;
         float wm[kFastItems];
         uint32_t wc[kFastItems];
         if (DKT >= 0) {
@@ -551,11 +593,13 @@ __global__ __launch_bounds__(kCombThreads) void k_comb_fast(const float* __restr
             uint32_t run = 0;
 #pragma unroll
             for (int q = 0; q < NH; ++q) {
-                const int k = k0 - D + q;
+                const int o = q - D;  // offset from k0
+                const int k = k0 + o;
+                const int pidx = s0 + o + (o < 0 ? -1 : (o >= kFastItems ? 1 : 0));
                 const bool in = k >= 0 && k < K;
-                hv[q] = in ? sP[pad16(k)] : 0.0f;
-                const uint32_t c = in ? (sW[pad16(k)] & 0xFFu) : kCodeAbove;
-                if (q >= D && q < D + kFastItems) own[q - D] = c;
+                hv[q] = (o >= 0 && o < kFastItems) ? v[o] : (in ? sP[pidx] : 0.0f);
+                const uint32_t c = in ? sW[pidx] : kCodeAbove;
+                if (o >= 0 && o < kFastItems) own[o] = c;
                 run += c == kCodeBelow ? 1u : (c < kCodeCand ? (0x40u | ((c + 1u) << 12)) : 0u);
                 cum[q] = run;
             }
@@ -564,39 +608,38 @@ __global__ __launch_bounds__(kCombThreads) void k_comb_fast(const float* __restr
                 float mx = hv[j];
 #pragma unroll
                 for (int q = 1; q <= 2 * D; ++q) mx = fmaxf(mx, hv[j + q]);
-                const uint32_t sum = cum[j + 2 * D] - (j > 0 ? cum[j - 1] : 0u);
+                const uint32_t sm = cum[j + 2 * D] - (j > 0 ? cum[j - 1] : 0u);
                 wm[j] = mx;
-                wc[j] = own[j] | (sum << 8);
+                wc[j] = own[j] | (sm << 8);
             }
         } else {
 #pragma unroll
             for (int j = 0; j < kFastItems; ++j) {
                 const int k = k0 + j;
                 float mx = 0.0f;
-                uint32_t sum = 0, own = kCodeAbove;
+                uint32_t sm = 0, own = kCodeAbove;
                 if (k < K) {
-                    own = sW[pad16(k)] & 0xFFu;
+                    own = sW[s0 + j];
                     if (k >= dk && k + dk <= K - 1) {
                         mx = sP[pad16(k - dk)];
                         for (int q = -dk; q <= dk; ++q) {
                             mx = fmaxf(mx, sP[pad16(k + q)]);
-                            const uint32_t c = sW[pad16(k + q)] & 0xFFu;
-                            sum += c == kCodeBelow ? 1u
-                                 : (c < kCodeCand ? (0x40u | ((c + 1u) << 12)) : 0u);
+                            const uint32_t c = sW[pad16(k + q)];
+                            sm += c == kCodeBelow ? 1u
+                                : (c < kCodeCand ? (0x40u | ((c + 1u) << 12)) : 0u);
                         }
                     }
                 }
                 wm[j] = mx;
-                wc[j] = own | (sum << 8);
+                wc[j] = own | (sm << 8);
             }
         }
         __syncthreads();  // every read of the old arrays is done
 #pragma unroll
         for (int j = 0; j < kFastItems; ++j) {
-            const int k = k0 + j;
-            if (k < K) {
-                sP[pad16(k)] = wm[j];
-                sW[pad16(k)] = wc[j];
+            if (j < nmine) {
+                sP[s0 + j] = wm[j];
+                sW[s0 + j] = wc[j];
             }
         }
     }
@@ -607,101 +650,182 @@ __global__ __launch_bounds__(kCombThreads) void k_comb_fast(const float* __restr
     const int bw = ca.b_hi - ca.b_lo;
     float best = 0.0f;
     int best_i = -1;
-    for (int i = dk + tid; i <= i_max; i += kCombThreads) {
-        auto centre = [&](int m) -> int {
-            if (ca.g >= 0) return (m - 1) * (int)ca.g + m * i;
-            const double num = (double)(m - 1) * (double)ca.f0 + (double)m * (double)i * (double)ca.df;
-            return (int)floor(num / (double)ca.df + 0.5);
-        };
-        int mv = 0;
-        bool slow = false;  // overlapping windows, or a window with several in-band bins
-        int prev_c = -1;
-#pragma unroll
-        for (int m = 1; m <= (MT > 0 ? MT : 32); ++m) {
-            if (m > M) break;
+    // Complement median's band index by a scan of the distinct window bins'
+    // own codes (overlapping windows, or windows with several in-band bins).
+    auto scan_q = [&](auto&& centre, int mv, int& hsize) -> int {
+        int below = 0;
+        hsize = 0;
+        int ph = -1;
+        for (int m = 1; m <= mv; ++m) {
             const int cm = centre(m);
-            if (cm + dk > K - 1) break;
-            if (m > 1 && cm - prev_c <= 2 * dk) slow = true;
-            prev_c = cm;
-            mv = m;
-        }
-        float snr = 0.0f;
-        if (mv >= ca.h_min) {
-            float smax = 0.0f;
-            int below = 0;
-            int inr[MI];
-#pragma unroll
-            for (int j = 0; j < MI; ++j) inr[j] = 0x7FFF;
-#pragma unroll
-            for (int m = 1; m <= (MT > 0 ? MT : 32); ++m) {
-                if (m > mv) break;
-                const int cm = centre(m);
-                smax += sP[pad16(cm)];
-                const uint32_t w = sW[pad16(cm)];
-                below += (int)((w >> 8) & 0x3Fu);
-                const uint32_t wi = (w >> 14) & 0x3Fu;
-                if (wi == 1u && m <= MI) inr[m - 1] = (int)((w >> 20) & 0xFFFu) - 1;
-                else if (wi != 0u) slow = true;
+            const int lo = (cm - dk) > ph + 1 ? (cm - dk) : ph + 1;
+            for (int k = lo; k <= cm + dk; ++k) {
+                ++hsize;
+                below += (sW[pad16(k)] & 0xFFu) == kCodeBelow ? 1 : 0;
             }
-            int hsize = mv * (2 * dk + 1);
-            int q;
-            if (!slow) {
-                const int r = (K - hsize - 1) / 2;
-                const int t = r + below - ca.b_lo;
-                // band index of the median: smallest q with q = t + #(window band indices <= q)
-                q = t;
-#pragma unroll
-                for (int iter = 0; iter <= MI; ++iter) {
-                    int extra = 0;
-#pragma unroll
-                    for (int j = 0; j < MI; ++j) extra += inr[j] <= q ? 1 : 0;
-                    q = t + extra;
+            ph = cm + dk;
+        }
+        const int t = (K - hsize - 1) / 2 + below - ca.b_lo;
+        int q = t;
+        const int hmax = M * (2 * dk + 1);
+        for (int iter = 0; iter <= hmax + 1; ++iter) {
+            int extra = 0;
+            ph = -1;
+            for (int m = 1; m <= mv; ++m) {
+                const int cm = centre(m);
+                const int lo = (cm - dk) > ph + 1 ? (cm - dk) : ph + 1;
+                for (int k = lo; k <= cm + dk; ++k) {
+                    const uint32_t c = sW[pad16(k)] & 0xFFu;
+                    if (c < kCodeCand && (int)c <= q) ++extra;
                 }
-            } else {
-                // distinct window bins, scanned with their own codes
-                below = 0;
-                hsize = 0;
-                int ph = -1;
+                ph = cm + dk;
+            }
+            if (t + extra == q) break;
+            q = t + extra;
+        }
+        return q;
+    };
+    auto finish = [&](int i, float smax, int mv, int hsize, int q) {
+        float med = 0.0f;
+        if (K - hsize > 0) {
+            q = q < 0 ? 0 : (q > bw ? bw : q);
+            med = sBand[q];
+        }
+        const float N = smax / (float)mv;
+        const float den = med > fden_floor ? med : fden_floor;
+        const float snr = den > 0.0f ? __fdividef(N, den) : 0.0f;
+        if (best_i < 0 || snr > best) { best = snr; best_i = i; }
+        return snr;
+    };
+    if (MT > 0 && ca.g >= 0) {
+        // integer grid ratio g = f0 / df: centres c_m = m (g + i) - g, equally spaced
+        const int g = (int)ca.g;
+        const int wlen = 2 * dk + 1;
+        for (int i = dk + tid; i <= i_max; i += kCombThreads) {
+            const int step = g + i;
+            int mv = 0;
+#pragma unroll
+            for (int m = 1; m <= MI; ++m) mv += (m * step - g + dk <= K - 1) ? 1 : 0;
+            float snr = 0.0f;
+            if (mv >= ca.h_min) {
+                float smax = 0.0f;
+                int below = 0;
+                const bool overlap = step <= 2 * dk;
+                bool multi = false;  // a window holds several in-band bins
+                int inr[MI];
+                uint32_t wv[MI];
+#pragma unroll
+                for (int m = 1; m <= MI; ++m) {
+                    const bool val = m <= mv;
+                    const int cm = val ? m * step - g : dk;
+                    const int a = pad16(cm);
+                    const float wmx = sP[a];
+                    const uint32_t w = sW[a];
+                    const uint32_t wi = val ? (w >> 14) & 0x3Fu : 0u;
+                    wv[m - 1] = wi;
+                    smax += val ? wmx : 0.0f;
+                    below += val ? (int)((w >> 8) & 0x3Fu) : 0;
+                    inr[m - 1] = wi == 1u ? (int)((w >> 20) & 0xFFFu) - 1 : 0x7FFF;
+                    multi = multi || wi > 1u;
+                }
+                int hsize = mv * wlen;
+                int q;
+                if (!overlap && !multi) {
+                    // q = t + #(inr <= q): walk the window band indices in ascending order
+#pragma unroll
+                    for (int a = 0; a < MI; ++a)
+#pragma unroll
+                        for (int b = a + 1; b < MI; ++b) {
+                            const int lo = min(inr[a], inr[b]);
+                            const int hi = max(inr[a], inr[b]);
+                            inr[a] = lo;
+                            inr[b] = hi;
+                        }
+                    q = (K - hsize - 1) / 2 + below - ca.b_lo;
+#pragma unroll
+                    for (int a = 0; a < MI; ++a) q += inr[a] <= q ? 1 : 0;
+                } else if (!overlap) {
+                    // disjoint windows, some holding several in-band bins: fixed
+                    // point q = t + #(window band indices <= q), those windows scanned
+                    const int t = (K - hsize - 1) / 2 + below - ca.b_lo;
+                    q = t;
+                    for (int iter = 0; iter <= hsize; ++iter) {
+                        int extra = 0;
+#pragma unroll
+                        for (int m = 1; m <= MI; ++m) {
+                            if (wv[m - 1] == 1u) extra += inr[m - 1] <= q ? 1 : 0;
+                            else if (wv[m - 1] > 1u) {
+                                const int cm = m * step - g;
+                                for (int k = cm - dk; k <= cm + dk; ++k) {
+                                    const uint32_t c = sW[pad16(k)] & 0xFFu;
+                                    extra += (c < kCodeCand && (int)c <= q) ? 1 : 0;
+                                }
+                            }
+                        }
+                        if (t + extra == q) break;
+                        q = t + extra;
+                    }
+                } else {
+                    auto centre = [&](int m) -> int { return m * step - g; };
+                    q = scan_q(centre, mv, hsize);
+                }
+                snr = finish(i, smax, mv, hsize, q);
+            }
+            if (snr_all) snr_all[(int64_t)u * K + i] = snr;
+        }
+    } else {
+        for (int i = dk + tid; i <= i_max; i += kCombThreads) {
+            auto centre = [&](int m) -> int {
+                if (ca.g >= 0) return (m - 1) * (int)ca.g + m * i;
+                const double num =
+                    (double)(m - 1) * (double)ca.f0 + (double)m * (double)i * (double)ca.df;
+                return (int)floor(num / (double)ca.df + 0.5);
+            };
+            int mv = 0;
+            bool slow = false;
+            int prev_c = -1;
+            for (int m = 1; m <= M; ++m) {
+                const int cm = centre(m);
+                if (cm + dk > K - 1) break;
+                if (m > 1 && cm - prev_c <= 2 * dk) slow = true;
+                prev_c = cm;
+                mv = m;
+            }
+            float snr = 0.0f;
+            if (mv >= ca.h_min) {
+                float smax = 0.0f;
+                int below = 0;
+                int inr[kInbCap];
+#pragma unroll
+                for (int j = 0; j < kInbCap; ++j) inr[j] = 0x7FFF;
                 for (int m = 1; m <= mv; ++m) {
                     const int cm = centre(m);
-                    const int lo = (cm - dk) > ph + 1 ? (cm - dk) : ph + 1;
-                    for (int k = lo; k <= cm + dk; ++k) {
-                        ++hsize;
-                        below += (sW[pad16(k)] & 0xFFu) == kCodeBelow ? 1 : 0;
-                    }
-                    ph = cm + dk;
+                    smax += sP[pad16(cm)];
+                    const uint32_t w = sW[pad16(cm)];
+                    below += (int)((w >> 8) & 0x3Fu);
+                    const uint32_t wi = (w >> 14) & 0x3Fu;
+                    if (wi == 1u && m <= kInbCap) inr[m - 1] = (int)((w >> 20) & 0xFFFu) - 1;
+                    else if (wi != 0u) slow = true;
                 }
-                const int r = (K - hsize - 1) / 2;
-                const int t = r + below - ca.b_lo;
-                q = t;
-                const int hmax = M * (2 * dk + 1);
-                for (int iter = 0; iter <= hmax + 1; ++iter) {
-                    int extra = 0;
-                    ph = -1;
-                    for (int m = 1; m <= mv; ++m) {
-                        const int cm = centre(m);
-                        const int lo = (cm - dk) > ph + 1 ? (cm - dk) : ph + 1;
-                        for (int k = lo; k <= cm + dk; ++k) {
-                            const uint32_t c = sW[pad16(k)] & 0xFFu;
-                            if (c < kCodeCand && (int)c <= q) ++extra;
-                        }
-                        ph = cm + dk;
+                int hsize = mv * (2 * dk + 1);
+                int q;
+                if (!slow) {
+                    const int t = (K - hsize - 1) / 2 + below - ca.b_lo;
+                    q = t;
+                    for (int iter = 0; iter <= kInbCap; ++iter) {
+                        int extra = 0;
+#pragma unroll
+                        for (int j = 0; j < kInbCap; ++j) extra += inr[j] <= q ? 1 : 0;
+                        if (t + extra == q) break;
+                        q = t + extra;
                     }
-                    if (t + extra == q) break;
-                    q = t + extra;
+                } else {
+                    q = scan_q(centre, mv, hsize);
                 }
+                snr = finish(i, smax, mv, hsize, q);
             }
-            float med = 0.0f;
-            if (K - hsize > 0) {
-                q = q < 0 ? 0 : (q > bw ? bw : q);
-                med = sBand[q];
-            }
-            const float N = smax / (float)mv;
-            const float den = med > fden_floor ? med : fden_floor;
-            snr = den > 0.0f ? N / den : 0.0f;
-            if (best_i < 0 || snr > best) { best = snr; best_i = i; }
+            if (snr_all) snr_all[(int64_t)u * K + i] = snr;
         }
-        if (snr_all) snr_all[(int64_t)u * K + i] = snr;
     }
     if (snr_all) {
         for (int i = tid; i < K; i += kCombThreads)
