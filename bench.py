@@ -97,30 +97,39 @@ def _pmc_mean_kib(path, counter, name_part):
     return sum(vals) / len(vals), len(vals)
 
 
+TRAFFIC_KERNELS = {
+    # tag prefix: (kernel-name fragment, sources whose digest keys the record)
+    "ndft_mfma": ("k_ndft_mfma", ["ndft.hip", "ddhf_internal.h"]),
+    "ndft_valu": ("k_ndft_valu", ["ndft.hip", "ddhf_internal.h"]),
+    "comb_fast": ("k_comb_fast", ["comb.hip", "ddhf_internal.h"]),
+}
+
+
 def traffic_summary(args, fetch_csv, write_csv, cal_fetch_csv, cal_write_csv):
-    """HBM bytes per NDFT launch: FETCH_SIZE and WRITE_SIZE (KiB per dispatch),
-    each scaled by bytes / reading of the plain copy kernel."""
+    """HBM bytes per launch of the NDFT kernel and of the comb kernel: FETCH_SIZE
+    and WRITE_SIZE (KiB per dispatch), each scaled by bytes / reading of the
+    plain copy kernel."""
     if args.kernel not in ("valu", "mfma"):
         raise SystemExit("--traffic-summary needs --kernel valu or mfma")
-    name = f"k_ndft_{args.kernel}"
     cf, _ = _pmc_mean_kib(cal_fetch_csv, "FETCH_SIZE", "copyBuffer")
     cw, _ = _pmc_mean_kib(cal_write_csv, "WRITE_SIZE", "copyBuffer")
     fetch_scale = COPY_BYTES / (cf * 1024.0)
     write_scale = COPY_BYTES / (cw * 1024.0)
-    f, nf = _pmc_mean_kib(fetch_csv, "FETCH_SIZE", name)
-    w, nw = _pmc_mean_kib(write_csv, "WRITE_SIZE", name)
-    rec = {"kernel": name, "workload": args.workload,
-           "source_digest": kernel_source_digest(["ndft.hip", "ddhf_internal.h"]),
-           "fetch_kib_per_dispatch": f, "write_kib_per_dispatch": w, "dispatches": [nf, nw],
-           "copy_fetch_kib": cf, "copy_write_kib": cw,
-           "fetch_scale": fetch_scale, "write_scale": write_scale,
-           "bytes_per_launch": f * 1024.0 * fetch_scale + w * 1024.0 * write_scale}
-    tag = f"ndft_{args.kernel}_{args.workload}"
-    out = os.path.join(ROOT, "profiles", f"traffic_{tag}.json")
-    with open(out, "w") as fo:
-        json.dump(rec, fo, indent=1)
-        fo.write("\n")
-    print(json.dumps(rec), flush=True)
+    for prefix in (f"ndft_{args.kernel}", "comb_fast"):
+        name, srcs = TRAFFIC_KERNELS[prefix]
+        f, nf = _pmc_mean_kib(fetch_csv, "FETCH_SIZE", name)
+        w, nw = _pmc_mean_kib(write_csv, "WRITE_SIZE", name)
+        rec = {"kernel": name, "workload": args.workload,
+               "source_digest": kernel_source_digest(srcs),
+               "fetch_kib_per_dispatch": f, "write_kib_per_dispatch": w, "dispatches": [nf, nw],
+               "copy_fetch_kib": cf, "copy_write_kib": cw,
+               "fetch_scale": fetch_scale, "write_scale": write_scale,
+               "bytes_per_launch": f * 1024.0 * fetch_scale + w * 1024.0 * write_scale}
+        out = os.path.join(ROOT, "profiles", f"traffic_{prefix}_{args.workload}.json")
+        with open(out, "w") as fo:
+            json.dump(rec, fo, indent=1)
+            fo.write("\n")
+        print(json.dumps(rec), flush=True)
 
 
 def kernel_source_digest(names):
@@ -333,8 +342,22 @@ def main():
     flops = FLOP_PER_EVENT_BIN * ev_bins
     achieved_tflops = flops / (ndft_ms * 1e-3) / 1e12
     tag = "ndft_valu" if launch.kernel == D.DDHF_KERNEL_VALU else "ndft_mfma"
-    digest = kernel_source_digest(["ndft.hip", "ddhf_internal.h"])
-    traffic = load_traffic(f"{tag}_{args.workload}", digest)
+    traffic = load_traffic(f"{tag}_{args.workload}",
+                           kernel_source_digest(TRAFFIC_KERNELS[tag][1]))
+    roof_ndft = {"bound": "alu" if launch.kernel == D.DDHF_KERNEL_VALU else "mfma",
+                 "kernel": TRAFFIC_KERNELS[tag][0], "achieved": achieved_tflops,
+                 "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
+                 "frac": achieved_tflops / FP32_PEAK_TFLOPS, "traffic": traffic,
+                 "ms": ndft_ms, "algorithmic": f"{FLOP_PER_EVENT_BIN} FLOP x {ev_bins} event-bins"}
+    comb_ms = float(np.mean(stage_ms["comb"]))
+    comb_bytes = na * K * 4 + na * 12          # read P once; write sf, snr, bin
+    comb_gbs = comb_bytes / (comb_ms * 1e-3) / 1e9
+    roof_comb = {"bound": "hbm", "kernel": "k_comb_fast", "achieved": comb_gbs,
+                 "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": comb_gbs / HBM_PEAK_GBS,
+                 "traffic": load_traffic(f"comb_fast_{args.workload}",
+                                         kernel_source_digest(TRAFFIC_KERNELS["comb_fast"][1])),
+                 "ms": comb_ms, "algorithmic": f"{comb_bytes} bytes (P read + per-pixel outputs)"}
+    dominant = roof_ndft if ndft_ms >= comb_ms else roof_comb
 
     out = {
         "metric": "NDFT pixel*bins/s (% FP32 VALU peak) + p50/p99 frame latency, 1280x720",
@@ -363,10 +386,8 @@ def main():
                              "p99": float(np.percentile(frame_ms, 99)),
                              "path": "whole 100 ms window recomputed per frame, inputs resident"},
         "boxes": nbox,
-        "roofline": {"bound": "alu" if launch.kernel == D.DDHF_KERNEL_VALU else "mfma",
-                     "kernel": tag, "achieved": achieved_tflops, "peak": FP32_PEAK_TFLOPS,
-                     "unit": "TFLOP/s", "frac": achieved_tflops / FP32_PEAK_TFLOPS,
-                     "traffic": traffic},
+        "roofline": dominant,
+        "rooflines": {"ndft": roof_ndft, "comb": roof_comb},
     }
     if args.stream_steps > 0:
         print("[bench] stream leg", file=sys.stderr, flush=True)

@@ -31,6 +31,7 @@ struct CombArgs {
     int32_t kpad;     // K rounded up to a multiple of 4
 };
 
+template <int NT = kCombThreads>
 __device__ __forceinline__ double block_sum_d(double v, double* red) {
     v = wave_sum(v);
     const int w = threadIdx.x / kWave;
@@ -39,7 +40,7 @@ __device__ __forceinline__ double block_sum_d(double v, double* red) {
     __syncthreads();
     double t = 0.0;
 #pragma unroll
-    for (int k = 0; k < kCombThreads / kWave; ++k) t += red[k];
+    for (int k = 0; k < NT / kWave; ++k) t += red[k];
     return t;
 }
 
@@ -348,13 +349,18 @@ __global__ __launch_bounds__(kCombThreads) void k_comb(const float* __restrict__
 // LDS arrays indexed by bin carry one padding word per 16 bins and histograms
 // one per 8 buckets, so segment walks and histogram scans are conflict-free.
 // ---------------------------------------------------------------------------
+constexpr int kFT = 256;           // threads per pixel
 constexpr int kFastItems = 16;     // bins per thread: K <= 4096
+constexpr int kSegShift = 4;       // log2(kFastItems)
+static_assert(kFT * kFastItems == 4096 && (1 << kSegShift) == kFastItems, "fast comb shape");
+static_assert(kFT >= 256 && (2 * 2304) % kFT == 0, "fast comb histogram layout");
 constexpr int kListCap = 512;
 constexpr int kInbCap = 8;         // in-band window bins kept in registers per candidate
 constexpr int kHistWords = 2048 + 256;
 constexpr uint32_t kCodeCand = 0xFDu, kCodeBelow = 0xFEu, kCodeAbove = 0xFFu;
 
-__device__ __forceinline__ int pad16(int k) { return k + (k >> 4); }
+// one padding word after every thread segment
+__device__ __forceinline__ int padk(int k) { return k + (k >> kSegShift); }
 
 struct Loc {
     int d;
@@ -373,8 +379,8 @@ __device__ __forceinline__ void locate2048x2(const uint32_t* h1, uint32_t base1,
     uint32_t s1 = 0, s2 = 0;
 #pragma unroll
     for (int i = 0; i < 8; ++i) {
-        c1[i] = h1[tid * 9 + i];
-        c2[i] = SAME ? c1[i] : h2[tid * 9 + i];
+        c1[i] = tid < 256 ? h1[tid * 9 + i] : 0u;  // 8 buckets for each of the first 256 threads
+        c2[i] = SAME ? c1[i] : (tid < 256 ? h2[tid * 9 + i] : 0u);
         s1 += c1[i];
         s2 += c2[i];
     }
@@ -383,14 +389,14 @@ __device__ __forceinline__ void locate2048x2(const uint32_t* h1, uint32_t base1,
     const int w = tid / kWave;
     if (__lane_id() == kWave - 1) {
         scr[w] = i1;
-        scr[kCombThreads / kWave + w] = i2;
+        scr[kFT / kWave + w] = i2;
     }
     __syncthreads();
     uint32_t r1 = base1 + i1 - s1, r2 = base2 + i2 - s2;
 #pragma unroll
-    for (int k = 0; k < kCombThreads / kWave - 1; ++k) {
+    for (int k = 0; k < kFT / kWave - 1; ++k) {
         r1 += k < w ? scr[k] : 0u;
-        r2 += k < w ? scr[kCombThreads / kWave + k] : 0u;
+        r2 += k < w ? scr[kFT / kWave + k] : 0u;
     }
 #pragma unroll
     for (int i = 0; i < 8; ++i) {
@@ -403,7 +409,7 @@ __device__ __forceinline__ void locate2048x2(const uint32_t* h1, uint32_t base1,
 }
 
 template <int MT, int DKT>
-__global__ __launch_bounds__(kCombThreads) void k_comb_fast(const float* __restrict__ power,
+__global__ __launch_bounds__(kFT) void k_comb_fast(const float* __restrict__ power,
                                                             int32_t n_active, CombArgs ca,
                                                             int32_t i_max,
                                                             float* __restrict__ sf_out,
@@ -412,16 +418,16 @@ __global__ __launch_bounds__(kCombThreads) void k_comb_fast(const float* __restr
                                                             float* __restrict__ snr_all,
                                                             const int32_t* __restrict__ n_dev) {
     extern __shared__ __align__(16) char smem[];
-    float* sP = (float*)smem;                 // [pad16(K)]: spectrum, then window maxima
+    float* sP = (float*)smem;                 // [padk(K)]: spectrum, then window maxima
     uint32_t* sW = (uint32_t*)(sP + ca.kpad); // [2 kHistWords]: histograms, then code words
     __shared__ float sBand[256];
     __shared__ uint16_t sList[kListCap];
-    __shared__ double red[kCombThreads / kWave];
-    __shared__ uint32_t scr[2 * kCombThreads / kWave];
+    __shared__ double red[kFT / kWave];
+    __shared__ uint32_t scr[2 * kFT / kWave];
     __shared__ Loc l1lo, l1hi, l2lo, l2hi;
     __shared__ uint32_t s_nlist;
-    __shared__ float s_best[kCombThreads / kWave];
-    __shared__ int s_bi[kCombThreads / kWave];
+    __shared__ float s_best[kFT / kWave];
+    __shared__ int s_bi[kFT / kWave];
 
     const int K = ca.K;
     const int M = MT > 0 ? MT : ca.M;
@@ -440,19 +446,19 @@ __global__ __launch_bounds__(kCombThreads) void k_comb_fast(const float* __restr
         float g[kFastItems];
 #pragma unroll
         for (int i = 0; i < kFastItems; ++i) {
-            const int k = tid + i * kCombThreads;
+            const int k = tid + i * kFT;
             g[i] = k < K ? row[k] : 0.0f;
         }
 #pragma unroll
-        for (int i = 0; i < 2 * kHistWords / kCombThreads; ++i) sW[tid + i * kCombThreads] = 0u;
+        for (int i = 0; i < 2 * kHistWords / kFT; ++i) sW[tid + i * kFT] = 0u;
         if (tid == 0) {
             l1lo = l1hi = l2lo = l2hi = Loc{0, 0};
             s_nlist = 0;
         }
-        const int ps = pad16(tid);
+        const int ps = padk(tid);
 #pragma unroll
         for (int i = 0; i < kFastItems; ++i)
-            if (tid + i * kCombThreads < K) sP[ps + i * (kCombThreads + kCombThreads / 16)] = g[i];
+            if (tid + i * kFT < K) sP[ps + i * (kFT + (kFT >> kSegShift))] = g[i];
     }
     __syncthreads();
     float v[kFastItems];
@@ -471,13 +477,13 @@ __global__ __launch_bounds__(kCombThreads) void k_comb_fast(const float* __restr
             atomicAdd(&hA[d1 + (d1 >> 3)], 1u);
         }
     }
-    const double sum = block_sum_d((double)fsum, red);
+    const double sum = block_sum_d<kFT>((double)fsum, red);
     const double mean = sum / (double)K;
     const float floor_v = (float)(ca.eps * mean);
     locate2048x2<true>(hA, 0, ca.b_lo, &l1lo, hA, 0, ca.b_hi, &l1hi, scr);
     const uint32_t d1lo = (uint32_t)l1lo.d, d1hi = (uint32_t)l1hi.d;
 #pragma unroll
-    for (int i = 0; i < 2 * kHistWords / kCombThreads; ++i) sW[tid + i * kCombThreads] = 0u;
+    for (int i = 0; i < 2 * kHistWords / kFT; ++i) sW[tid + i * kFT] = 0u;
     __syncthreads();
     // ---- log-sum (Eq. 7) and second digit (bits 9..19) ----------------------
     double sl = 0.0;
@@ -492,7 +498,7 @@ __global__ __launch_bounds__(kCombThreads) void k_comb_fast(const float* __restr
             if (d1 == d1hi) atomicAdd(&hB[d2 + (d2 >> 3)], 1u);
         }
     }
-    sl = block_sum_d(sl, red);
+    sl = block_sum_d<kFT>(sl, red);
     if (tid == 0) sf_out[u] = mean > 0.0 ? (float)exp2(sl / (double)K - log2(mean)) : 1.0f;
     locate2048x2<false>(hA, l1lo.before, ca.b_lo, &l2lo, hB, l1hi.before, ca.b_hi, &l2hi, scr);
     const uint32_t key_lo = (d1lo << 11) | (uint32_t)l2lo.d;
@@ -519,7 +525,7 @@ __global__ __launch_bounds__(kCombThreads) void k_comb_fast(const float* __restr
         if (tid < kWave) {
             const bool mine = tid < nL;
             const int ki = mine ? (int)sList[tid] : 0;
-            const float vi = mine ? sP[pad16(ki)] : 0.0f;
+            const float vi = mine ? sP[padk(ki)] : 0.0f;
             uint32_t r = 0;
             for (int b = 0; b < nL; ++b) {
                 const float vj = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(vi), b));
@@ -532,17 +538,17 @@ __global__ __launch_bounds__(kCombThreads) void k_comb_fast(const float* __restr
                 if (full < ca.b_lo) code = kCodeBelow;
                 else if (full > ca.b_hi) code = kCodeAbove;
                 else { code = (uint32_t)(full - ca.b_lo); sBand[full - ca.b_lo] = vi; }
-                sW[pad16(ki)] = code;
+                sW[padk(ki)] = code;
             }
         }
     } else if (nL <= kListCap) {
-        for (int a = tid; a < nL; a += kCombThreads) {
+        for (int a = tid; a < nL; a += kFT) {
             const int ki = sList[a];
-            const float vi = sP[pad16(ki)];
+            const float vi = sP[padk(ki)];
             uint32_t r = 0;
             for (int b = 0; b < nL; ++b) {
                 const int kj = sList[b];
-                const float vj = sP[pad16(kj)];
+                const float vj = sP[padk(kj)];
                 r += (vj < vi || (vj == vi && kj < ki)) ? 1u : 0u;
             }
             const int full = (int)(below_base + r);
@@ -550,7 +556,7 @@ __global__ __launch_bounds__(kCombThreads) void k_comb_fast(const float* __restr
             if (full < ca.b_lo) code = kCodeBelow;
             else if (full > ca.b_hi) code = kCodeAbove;
             else { code = (uint32_t)(full - ca.b_lo); sBand[full - ca.b_lo] = vi; }
-            sW[pad16(ki)] = code;
+            sW[padk(ki)] = code;
         }
     } else {
         // many exact ties: rank each candidate bin against all candidate bins
@@ -563,7 +569,7 @@ __global__ __launch_bounds__(kCombThreads) void k_comb_fast(const float* __restr
             const float vi = v[j];
             uint32_t r = 0;
             for (int kj = 0; kj < K; ++kj) {
-                const float vj = sP[pad16(kj)];
+                const float vj = sP[padk(kj)];
                 const uint32_t kk = (__float_as_uint(vj) >> 9) & 0x3FFFFFu;
                 if (kk >= key_lo && kk <= key_hi && (vj < vi || (vj == vi && kj < ki))) ++r;
             }
@@ -621,10 +627,10 @@ __global__ __launch_bounds__(kCombThreads) void k_comb_fast(const float* __restr
                 if (k < K) {
                     own = sW[s0 + j];
                     if (k >= dk && k + dk <= K - 1) {
-                        mx = sP[pad16(k - dk)];
+                        mx = sP[padk(k - dk)];
                         for (int q = -dk; q <= dk; ++q) {
-                            mx = fmaxf(mx, sP[pad16(k + q)]);
-                            const uint32_t c = sW[pad16(k + q)];
+                            mx = fmaxf(mx, sP[padk(k + q)]);
+                            const uint32_t c = sW[padk(k + q)];
                             sm += c == kCodeBelow ? 1u
                                 : (c < kCodeCand ? (0x40u | ((c + 1u) << 12)) : 0u);
                         }
@@ -661,7 +667,7 @@ __global__ __launch_bounds__(kCombThreads) void k_comb_fast(const float* __restr
             const int lo = (cm - dk) > ph + 1 ? (cm - dk) : ph + 1;
             for (int k = lo; k <= cm + dk; ++k) {
                 ++hsize;
-                below += (sW[pad16(k)] & 0xFFu) == kCodeBelow ? 1 : 0;
+                below += (sW[padk(k)] & 0xFFu) == kCodeBelow ? 1 : 0;
             }
             ph = cm + dk;
         }
@@ -675,7 +681,7 @@ __global__ __launch_bounds__(kCombThreads) void k_comb_fast(const float* __restr
                 const int cm = centre(m);
                 const int lo = (cm - dk) > ph + 1 ? (cm - dk) : ph + 1;
                 for (int k = lo; k <= cm + dk; ++k) {
-                    const uint32_t c = sW[pad16(k)] & 0xFFu;
+                    const uint32_t c = sW[padk(k)] & 0xFFu;
                     if (c < kCodeCand && (int)c <= q) ++extra;
                 }
                 ph = cm + dk;
@@ -701,7 +707,7 @@ __global__ __launch_bounds__(kCombThreads) void k_comb_fast(const float* __restr
         // integer grid ratio g = f0 / df: centres c_m = m (g + i) - g, equally spaced
         const int g = (int)ca.g;
         const int wlen = 2 * dk + 1;
-        for (int i = dk + tid; i <= i_max; i += kCombThreads) {
+        for (int i = dk + tid; i <= i_max; i += kFT) {
             const int step = g + i;
             int mv = 0;
 #pragma unroll
@@ -718,7 +724,7 @@ __global__ __launch_bounds__(kCombThreads) void k_comb_fast(const float* __restr
                 for (int m = 1; m <= MI; ++m) {
                     const bool val = m <= mv;
                     const int cm = val ? m * step - g : dk;
-                    const int a = pad16(cm);
+                    const int a = padk(cm);
                     const float wmx = sP[a];
                     const uint32_t w = sW[a];
                     const uint32_t wi = val ? (w >> 14) & 0x3Fu : 0u;
@@ -757,7 +763,7 @@ __global__ __launch_bounds__(kCombThreads) void k_comb_fast(const float* __restr
                             else if (wv[m - 1] > 1u) {
                                 const int cm = m * step - g;
                                 for (int k = cm - dk; k <= cm + dk; ++k) {
-                                    const uint32_t c = sW[pad16(k)] & 0xFFu;
+                                    const uint32_t c = sW[padk(k)] & 0xFFu;
                                     extra += (c < kCodeCand && (int)c <= q) ? 1 : 0;
                                 }
                             }
@@ -774,7 +780,7 @@ __global__ __launch_bounds__(kCombThreads) void k_comb_fast(const float* __restr
             if (snr_all) snr_all[(int64_t)u * K + i] = snr;
         }
     } else {
-        for (int i = dk + tid; i <= i_max; i += kCombThreads) {
+        for (int i = dk + tid; i <= i_max; i += kFT) {
             auto centre = [&](int m) -> int {
                 if (ca.g >= 0) return (m - 1) * (int)ca.g + m * i;
                 const double num =
@@ -800,8 +806,8 @@ __global__ __launch_bounds__(kCombThreads) void k_comb_fast(const float* __restr
                 for (int j = 0; j < kInbCap; ++j) inr[j] = 0x7FFF;
                 for (int m = 1; m <= mv; ++m) {
                     const int cm = centre(m);
-                    smax += sP[pad16(cm)];
-                    const uint32_t w = sW[pad16(cm)];
+                    smax += sP[padk(cm)];
+                    const uint32_t w = sW[padk(cm)];
                     below += (int)((w >> 8) & 0x3Fu);
                     const uint32_t wi = (w >> 14) & 0x3Fu;
                     if (wi == 1u && m <= kInbCap) inr[m - 1] = (int)((w >> 20) & 0xFFFu) - 1;
@@ -828,7 +834,7 @@ __global__ __launch_bounds__(kCombThreads) void k_comb_fast(const float* __restr
         }
     }
     if (snr_all) {
-        for (int i = tid; i < K; i += kCombThreads)
+        for (int i = tid; i < K; i += kFT)
             if (i < dk || i > i_max) snr_all[(int64_t)u * K + i] = 0.0f;
     }
 #pragma unroll
@@ -844,7 +850,7 @@ __global__ __launch_bounds__(kCombThreads) void k_comb_fast(const float* __restr
     if (tid == 0) {
         float b = 0.0f;
         int bi = -1;
-        for (int q = 0; q < kCombThreads / kWave; ++q) {
+        for (int q = 0; q < kFT / kWave; ++q) {
             const int oi = s_bi[q];
             if (oi >= 0 && (bi < 0 || s_best[q] > b || (s_best[q] == b && oi < bi))) {
                 b = s_best[q];
@@ -912,9 +918,9 @@ int comb_run(const float* power, int32_t n_active, const int32_t* n_dev, const d
     const int bw = ca.b_hi - ca.b_lo + 1;
     if (ca.K <= 4096 && bw <= 253) {
         CombArgs cf = ca;
-        cf.kpad = ((ca.K - 1) + ((ca.K - 1) >> 4) + 1 + 3) / 4 * 4;  // padded bin array
+        cf.kpad = ((ca.K - 1) + ((ca.K - 1) >> kSegShift) + 1 + 3) / 4 * 4;  // padded bin array
         const size_t lds = (size_t)cf.kpad * 4 + (size_t)2 * kHistWords * 4;
-        const dim3 gr((unsigned)n_active), bl(kCombThreads);
+        const dim3 gr((unsigned)n_active), bl(kFT);
         if (ca.M == 4 && ca.dk == 3)
             hipLaunchKernelGGL((k_comb_fast<4, 3>), gr, bl, lds, s, power, n_active, cf, i_max, sf,
                                snr_best, bin_best, snr_all, n_dev);
