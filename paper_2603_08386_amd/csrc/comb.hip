@@ -425,7 +425,7 @@ __global__ __launch_bounds__(kFT) void k_comb_fast(const float* __restrict__ pow
     __shared__ double red[kFT / kWave];
     __shared__ uint32_t scr[2 * kFT / kWave];
     __shared__ Loc l1lo, l1hi, l2lo, l2hi;
-    __shared__ uint32_t s_nlist;
+    __shared__ uint32_t s_nlist, s_qn;
     __shared__ float s_best[kFT / kWave];
     __shared__ int s_bi[kFT / kWave];
 
@@ -454,6 +454,7 @@ __global__ __launch_bounds__(kFT) void k_comb_fast(const float* __restrict__ pow
         if (tid == 0) {
             l1lo = l1hi = l2lo = l2hi = Loc{0, 0};
             s_nlist = 0;
+            s_qn = 0;
         }
         const int ps = padk(tid);
 #pragma unroll
@@ -700,26 +701,71 @@ __global__ __launch_bounds__(kFT) void k_comb_fast(const float* __restrict__ pow
         const float N = smax / (float)mv;
         const float den = med > fden_floor ? med : fden_floor;
         const float snr = den > 0.0f ? __fdividef(N, den) : 0.0f;
-        if (best_i < 0 || snr > best) { best = snr; best_i = i; }
+        // order-independent: highest score, lowest bin on ties
+        if (best_i < 0 || snr > best || (snr == best && i < best_i)) { best = snr; best_i = i; }
         return snr;
     };
     if (MT > 0 && ca.g >= 0) {
         // integer grid ratio g = f0 / df: centres c_m = m (g + i) - g, equally spaced
         const int g = (int)ca.g;
         const int wlen = 2 * dk + 1;
-        for (int i = dk + tid; i <= i_max; i += kFT) {
-            const int step = g + i;
+        auto nvalid = [&](int step) {
             int mv = 0;
 #pragma unroll
             for (int m = 1; m <= MI; ++m) mv += (m * step - g + dk <= K - 1) ? 1 : 0;
+            return mv;
+        };
+        // candidates with overlapping windows, or a window holding several
+        // in-band bins: fixed point over those windows' bins (or a full scan)
+        auto eval_slow = [&](int i) {
+            const int step = g + i;
+            const int mv = nvalid(step);
+            float smax = 0.0f;
+            int below = 0;
+            int hsize = mv * wlen;
+            int q;
+            if (step <= 2 * dk) {
+#pragma unroll
+                for (int m = 1; m <= MI; ++m)
+                    if (m <= mv) smax += sP[padk(m * step - g)];
+                auto centre = [&](int m) -> int { return m * step - g; };
+                q = scan_q(centre, mv, hsize);
+            } else {
+#pragma unroll
+                for (int m = 1; m <= MI; ++m)
+                    if (m <= mv) {
+                        const int a = padk(m * step - g);
+                        smax += sP[a];
+                        below += (int)((sW[a] >> 8) & 0x3Fu);
+                    }
+                const int t = (K - hsize - 1) / 2 + below - ca.b_lo;
+                q = t;
+                for (int iter = 0; iter <= hsize; ++iter) {
+                    int extra = 0;
+                    for (int m = 1; m <= mv; ++m) {
+                        const int cm = m * step - g;
+                        for (int k = cm - dk; k <= cm + dk; ++k) {
+                            const uint32_t c = sW[padk(k)] & 0xFFu;
+                            extra += (c < kCodeCand && (int)c <= q) ? 1 : 0;
+                        }
+                    }
+                    if (t + extra == q) break;
+                    q = t + extra;
+                }
+            }
+            const float snr = finish(i, smax, mv, hsize, q);
+            if (snr_all) snr_all[(int64_t)u * K + i] = snr;
+        };
+        // exact score of one candidate; updates this thread's best
+        auto eval_fast = [&](int i) {
+            const int step = g + i;
+            const int mv = nvalid(step);
             float snr = 0.0f;
             if (mv >= ca.h_min) {
                 float smax = 0.0f;
                 int below = 0;
-                const bool overlap = step <= 2 * dk;
-                bool multi = false;  // a window holds several in-band bins
+                bool slow = step <= 2 * dk;  // windows overlap
                 int inr[MI];
-                uint32_t wv[MI];
 #pragma unroll
                 for (int m = 1; m <= MI; ++m) {
                     const bool val = m <= mv;
@@ -728,56 +774,87 @@ __global__ __launch_bounds__(kFT) void k_comb_fast(const float* __restrict__ pow
                     const float wmx = sP[a];
                     const uint32_t w = sW[a];
                     const uint32_t wi = val ? (w >> 14) & 0x3Fu : 0u;
-                    wv[m - 1] = wi;
                     smax += val ? wmx : 0.0f;
                     below += val ? (int)((w >> 8) & 0x3Fu) : 0;
                     inr[m - 1] = wi == 1u ? (int)((w >> 20) & 0xFFFu) - 1 : 0x7FFF;
-                    multi = multi || wi > 1u;
+                    slow = slow || wi > 1u;
                 }
-                int hsize = mv * wlen;
-                int q;
-                if (!overlap && !multi) {
-                    // q = t + #(inr <= q): walk the window band indices in ascending order
+                if (slow) {
+                    eval_slow(i);
+                    return;
+                }
+                const int hsize = mv * wlen;
+                // q = t + #(inr <= q): walk the window band indices in ascending order
 #pragma unroll
-                    for (int a = 0; a < MI; ++a)
+                for (int a = 0; a < MI; ++a)
 #pragma unroll
-                        for (int b = a + 1; b < MI; ++b) {
-                            const int lo = min(inr[a], inr[b]);
-                            const int hi = max(inr[a], inr[b]);
-                            inr[a] = lo;
-                            inr[b] = hi;
-                        }
-                    q = (K - hsize - 1) / 2 + below - ca.b_lo;
-#pragma unroll
-                    for (int a = 0; a < MI; ++a) q += inr[a] <= q ? 1 : 0;
-                } else if (!overlap) {
-                    // disjoint windows, some holding several in-band bins: fixed
-                    // point q = t + #(window band indices <= q), those windows scanned
-                    const int t = (K - hsize - 1) / 2 + below - ca.b_lo;
-                    q = t;
-                    for (int iter = 0; iter <= hsize; ++iter) {
-                        int extra = 0;
-#pragma unroll
-                        for (int m = 1; m <= MI; ++m) {
-                            if (wv[m - 1] == 1u) extra += inr[m - 1] <= q ? 1 : 0;
-                            else if (wv[m - 1] > 1u) {
-                                const int cm = m * step - g;
-                                for (int k = cm - dk; k <= cm + dk; ++k) {
-                                    const uint32_t c = sW[padk(k)] & 0xFFu;
-                                    extra += (c < kCodeCand && (int)c <= q) ? 1 : 0;
-                                }
-                            }
-                        }
-                        if (t + extra == q) break;
-                        q = t + extra;
+                    for (int b = a + 1; b < MI; ++b) {
+                        const int lo = min(inr[a], inr[b]);
+                        const int hi = max(inr[a], inr[b]);
+                        inr[a] = lo;
+                        inr[b] = hi;
                     }
-                } else {
-                    auto centre = [&](int m) -> int { return m * step - g; };
-                    q = scan_q(centre, mv, hsize);
-                }
+                int q = (K - hsize - 1) / 2 + below - ca.b_lo;
+#pragma unroll
+                for (int a = 0; a < MI; ++a) q += inr[a] <= q ? 1 : 0;
                 snr = finish(i, smax, mv, hsize, q);
             }
             if (snr_all) snr_all[(int64_t)u * K + i] = snr;
+        };
+        // Every candidate's median lies in [sBand[0], sBand[bw]], so its score
+        // lies in [N / den_hi, N / den_lo].  Only candidates whose upper bound
+        // reaches the largest lower bound can be the argmax; the others need no
+        // median (unless every score is requested).
+        const float den_lo = fmaxf(sBand[0], fden_floor);
+        const float den_hi = fmaxf(sBand[bw], fden_floor);
+        if (snr_all == nullptr && den_lo > 0.0f) {
+            constexpr int kIt = 4096 / kFT;  // candidate rounds per thread, i < K <= 4096
+            float nv[kIt];
+            float lb = 0.0f;
+            const float r_hi = 1.0f / den_hi, r_lo = 1.0f / den_lo;
+#pragma unroll
+            for (int r = 0; r < kIt; ++r) {
+                const int i = dk + tid + r * kFT;
+                nv[r] = -1.0f;
+                if (i <= i_max) {
+                    const int step = g + i;
+                    const int mv = nvalid(step);
+                    if (mv >= ca.h_min) {
+                        float smax = 0.0f;
+#pragma unroll
+                        for (int m = 1; m <= MI; ++m) {
+                            const bool val = m <= mv;
+                            const float wmx = sP[padk(val ? m * step - g : dk)];
+                            smax += val ? wmx : 0.0f;
+                        }
+                        nv[r] = smax / (float)mv;  // the N of the exact evaluation
+                        lb = fmaxf(lb, nv[r] * r_hi);
+                    }
+                }
+            }
+#pragma unroll
+            for (int d = 32; d >= 1; d >>= 1) lb = fmaxf(lb, __shfl_xor(lb, d, 64));
+            if (__lane_id() == 0) s_best[tid / kWave] = lb;
+            __syncthreads();
+            float thr = 0.0f;
+#pragma unroll
+            for (int q = 0; q < kFT / kWave; ++q) thr = fmaxf(thr, s_best[q]);
+            thr *= 0.999f;  // margin over the rounding of both bounds
+#pragma unroll
+            for (int r = 0; r < kIt; ++r) {
+                if (nv[r] >= 0.0f && nv[r] * r_lo >= thr) {
+                    const int i = dk + tid + r * kFT;
+                    const uint32_t pos = atomicAdd(&s_qn, 1u);
+                    if (pos < kListCap) sList[pos] = (uint16_t)i;
+                    else eval_fast(i);
+                }
+            }
+            __syncthreads();
+            const int nq = (int)(s_qn < (uint32_t)kListCap ? s_qn : (uint32_t)kListCap);
+            for (int e = tid; e < nq; e += kFT) eval_fast((int)sList[e]);
+            __syncthreads();  // s_best is reused by the final reduction
+        } else {
+            for (int i = dk + tid; i <= i_max; i += kFT) eval_fast(i);
         }
     } else {
         for (int i = dk + tid; i <= i_max; i += kFT) {

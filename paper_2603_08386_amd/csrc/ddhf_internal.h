@@ -1,6 +1,8 @@
 // Internal helpers shared by the DDHF HIP sources (not part of the ABI).
 #pragma once
 #include <hip/hip_runtime.h>
+
+#include <type_traits>
 #include <stdint.h>
 #include <stddef.h>
 
@@ -52,21 +54,62 @@ __device__ __forceinline__ uint64_t lanemask_lt() {
     return l == 0 ? 0ull : ((~0ull) >> (64 - l));
 }
 
-// Inclusive prefix sum across the 64 lanes of a wave.
-__device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v) {
-#pragma unroll
-    for (int d = 1; d < 64; d <<= 1) {
-        uint32_t o = __shfl_up(v, d, 64);
-        if (__lane_id() >= d) v += o;
-    }
+// Cross-lane moves by DPP (GFX9 family): row_shr:n shifts within rows of 16
+// lanes, row_bcast:15 / row_bcast:31 pass lane 15 / lane 31 on to the next
+// rows.  Lanes whose source is out of range, or whose row is masked off,
+// receive 0 (old value 0, bound_ctrl set).
+template <int CTRL, int ROWMASK>
+__device__ __forceinline__ uint32_t dpp_u32(uint32_t v) {
+    return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, CTRL, ROWMASK, 0xF, true);
+}
+
+template <int CTRL, int ROWMASK>
+__device__ __forceinline__ double dpp_f64(double v) {
+    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, ROWMASK, 0xF, true);
+    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, ROWMASK, 0xF, true);
+    return __hiloint2double(hi, lo);
+}
+
+template <int CTRL, int ROWMASK>
+__device__ __forceinline__ float dpp_f32(float v) {
+    return __int_as_float(
+        __builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, ROWMASK, 0xF, true));
+}
+
+// Inclusive prefix sum across the 64 lanes of a wave (Hillis-Steele inside
+// each row of 16 lanes, then row totals carried by row_bcast:15 / :31).
+template <typename T, typename Step>
+__device__ __forceinline__ T wave_scan_dpp(T v, Step step) {
+    v += step(v, std::integral_constant<int, 0x111>(), std::integral_constant<int, 0xF>());
+    v += step(v, std::integral_constant<int, 0x112>(), std::integral_constant<int, 0xF>());
+    v += step(v, std::integral_constant<int, 0x114>(), std::integral_constant<int, 0xF>());
+    v += step(v, std::integral_constant<int, 0x118>(), std::integral_constant<int, 0xF>());
+    v += step(v, std::integral_constant<int, 0x142>(), std::integral_constant<int, 0xA>());
+    v += step(v, std::integral_constant<int, 0x143>(), std::integral_constant<int, 0xC>());
     return v;
 }
 
-template <typename T>
-__device__ __forceinline__ T wave_sum(T v) {
-#pragma unroll
-    for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d, 64);
-    return v;
+__device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v) {
+    return wave_scan_dpp(v, [](uint32_t x, auto c, auto m) { return dpp_u32<decltype(c)::value, decltype(m)::value>(x); });
+}
+
+// Sum over the 64 lanes of a wave, returned in every lane (the inclusive scan's
+// lane 63, broadcast).  The addition order is fixed, so the result is
+// reproducible.
+__device__ __forceinline__ uint32_t wave_sum(uint32_t v) {
+    return (uint32_t)__builtin_amdgcn_readlane((int)wave_incl_scan(v), 63);
+}
+
+__device__ __forceinline__ float wave_sum(float v) {
+    v = wave_scan_dpp(v, [](float x, auto c, auto m) { return dpp_f32<decltype(c)::value, decltype(m)::value>(x); });
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 63));
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+    v = wave_scan_dpp(v, [](double x, auto c, auto m) { return dpp_f64<decltype(c)::value, decltype(m)::value>(x); });
+    const int lo = __builtin_amdgcn_readlane(__double2loint(v), 63);
+    const int hi = __builtin_amdgcn_readlane(__double2hiint(v), 63);
+    return __hiloint2double(hi, lo);
 }
 
 // ---- host entry points implemented in one file and used by another -------

@@ -206,6 +206,12 @@ def run_comb(P32, grid, prm, want_all=False):
 
 def comb_compare(P32, grid, prm, check_all=True):
     sf, snr, b, allv = run_comb(P32, grid, prm, want_all=True)
+    # without the per-candidate output the kernel skips candidates that cannot
+    # be the argmax: best score and bin must be the same bits
+    sf_p, snr_p, b_p = run_comb(P32, grid, prm, want_all=False)
+    assert np.array_equal(sf_p, sf)
+    assert np.array_equal(snr_p, snr)
+    assert np.array_equal(b_p, b)
     for u in range(P32.shape[0]):
         P = P32[u].astype(np.float64)
         sf64 = oracle.spectral_flatness(P, prm.eps_rel)
