@@ -333,54 +333,63 @@ __global__ __launch_bounds__(kCombThreads) void k_comb(const float* __restrict__
 // Fast path (K <= 4096, band <= 253 ranks).  One 256-thread workgroup per
 // pixel; thread t owns the contiguous bins [16 t, 16 t + 16).
 //   1. The row is loaded coalesced and transposed through LDS.  A two-level
-//      11-bit radix select on the top 22 bits of the FP32 bit patterns
-//      (monotone for P >= 0) finds the 22-bit keys of ranks b_lo and b_hi; the
-//      few values sharing those keys are ranked exactly by (value, bin).
+//      radix select on the top 21 bits of the FP32 bit patterns (monotone for
+//      P >= 0; 11 + 10 bits) finds the keys of ranks b_lo and b_hi; the few
+//      values sharing those keys are ranked exactly by (value, bin).
 //      Flatness (Eq. 7) rides along.
-//   2. Every bin gets a code: band index of its rank, or below / above.
-//   3. For every window centre c, the thread's segment plus a halo of dk bins
-//      gives the window maximum max P[c - dk .. c + dk] (stored in place of
-//      P[c]) and, packed into c's code word, the window's below-band count,
-//      in-band count and, when one bin is in band, its band index.
-//   4. A candidate whose harmonic windows do not overlap reads two words per
-//      harmonic; the complement median's band index q is the smallest
-//      solution of q = t + #(window band indices <= q).  Overlapping windows,
-//      or windows with several in-band bins, take a scan of the bin codes.
-// LDS arrays indexed by bin carry one padding word per 16 bins and histograms
-// one per 8 buckets, so segment walks and histogram scans are conflict-free.
+//   2. Every bin gets a one-byte code: band index of its rank, or below /
+//      above the band.
+//   3. The spectrum array is overwritten by the window maxima
+//      max P[c - dk .. c + dk] of every centre c.
+//   4. Every candidate's complement median lies in [band[0], band[bw]], so its
+//      score lies in [N / den_hi, N / den_lo] with N the mean of its window
+//      maxima.  Only candidates whose upper bound reaches the best lower bound
+//      can be the argmax; they alone get the exact median, from their window
+//      bins' codes: q = smallest band index with q = t + #(window band indices
+//      <= q).  If every score is requested, every candidate is evaluated.
+// The LDS footprint (spectrum + 9 KB) allows six workgroups per CU.  Arrays
+// indexed by bin carry one padding slot per 16 bins and histograms one per 8
+// buckets, so segment walks and histogram scans are free of bank conflicts.
 // ---------------------------------------------------------------------------
 constexpr int kFT = 256;           // threads per pixel
 constexpr int kFastItems = 16;     // bins per thread: K <= 4096
 constexpr int kSegShift = 4;       // log2(kFastItems)
 static_assert(kFT * kFastItems == 4096 && (1 << kSegShift) == kFastItems, "fast comb shape");
-static_assert(kFT >= 256 && (2 * 2304) % kFT == 0, "fast comb histogram layout");
 constexpr int kListCap = 512;
 constexpr int kInbCap = 8;         // in-band window bins kept in registers per candidate
-constexpr int kHistWords = 2048 + 256;
-constexpr uint32_t kCodeCand = 0xFDu, kCodeBelow = 0xFEu, kCodeAbove = 0xFFu;
+constexpr int kXWords = 2304;      // histogram / code region (words)
+constexpr int kH1 = 2048;          // level-1 buckets (bits 20..30)
+constexpr int kH2 = 1024;          // level-2 buckets (bits 10..19)
+constexpr int kCodeBytes = 4352;   // padk(4095) + 1, rounded
+constexpr int kListOff = kCodeBytes;                 // byte offset of the candidate list
+constexpr int kBandOff = kListOff + 2 * kListCap;    // byte offset of the band values
+static_assert(kBandOff + 4 * 256 <= 4 * kXWords, "fast comb LDS region");
+constexpr uint8_t kCodeCand = 0xFDu, kCodeBelow = 0xFEu, kCodeAbove = 0xFFu;
 
-// one padding word after every thread segment
+// one padding slot after every thread segment
 __device__ __forceinline__ int padk(int k) { return k + (k >> kSegShift); }
+__device__ __forceinline__ int pad8(int b) { return b + (b >> 3); }
 
 struct Loc {
     int d;
     uint32_t before;
 };
 
-// Bucket of rank tgt in a padded 2048-bucket histogram (8 buckets per thread,
-// `base` elements counted before it); one thread writes `out`.  Two
-// histograms / targets per call share the barriers.
-template <bool SAME>
-__device__ __forceinline__ void locate2048x2(const uint32_t* h1, uint32_t base1, int32_t tgt1,
-                                             Loc* out1, const uint32_t* h2, uint32_t base2,
-                                             int32_t tgt2, Loc* out2, uint32_t* scr) {
+// Bucket of rank tgt in a padded histogram of NB buckets (8 per thread for
+// the first NB / 8 threads; `base` elements counted before it); one thread
+// writes `out`.  Two histograms / targets share the barriers.
+template <int NB, bool SAME>
+__device__ __forceinline__ void locate_x2(const uint32_t* h1, uint32_t base1, int32_t tgt1,
+                                          Loc* out1, const uint32_t* h2, uint32_t base2,
+                                          int32_t tgt2, Loc* out2, uint32_t* scr) {
     const int tid = threadIdx.x;
+    const bool own = tid < NB / 8;
     uint32_t c1[8], c2[8];
     uint32_t s1 = 0, s2 = 0;
 #pragma unroll
     for (int i = 0; i < 8; ++i) {
-        c1[i] = tid < 256 ? h1[tid * 9 + i] : 0u;  // 8 buckets for each of the first 256 threads
-        c2[i] = SAME ? c1[i] : (tid < 256 ? h2[tid * 9 + i] : 0u);
+        c1[i] = own ? h1[tid * 9 + i] : 0u;
+        c2[i] = SAME ? c1[i] : (own ? h2[tid * 9 + i] : 0u);
         s1 += c1[i];
         s2 += c2[i];
     }
@@ -410,18 +419,18 @@ __device__ __forceinline__ void locate2048x2(const uint32_t* h1, uint32_t base1,
 
 template <int MT, int DKT>
 __global__ __launch_bounds__(kFT) void k_comb_fast(const float* __restrict__ power,
-                                                            int32_t n_active, CombArgs ca,
-                                                            int32_t i_max,
-                                                            float* __restrict__ sf_out,
-                                                            float* __restrict__ snr_out,
-                                                            int32_t* __restrict__ bin_out,
-                                                            float* __restrict__ snr_all,
-                                                            const int32_t* __restrict__ n_dev) {
+                                                   int32_t n_active, CombArgs ca, int32_t i_max,
+                                                   float* __restrict__ sf_out,
+                                                   float* __restrict__ snr_out,
+                                                   int32_t* __restrict__ bin_out,
+                                                   float* __restrict__ snr_all,
+                                                   const int32_t* __restrict__ n_dev) {
     extern __shared__ __align__(16) char smem[];
-    float* sP = (float*)smem;                 // [padk(K)]: spectrum, then window maxima
-    uint32_t* sW = (uint32_t*)(sP + ca.kpad); // [2 kHistWords]: histograms, then code words
-    __shared__ float sBand[256];
-    __shared__ uint16_t sList[kListCap];
+    float* sP = (float*)smem;                       // [kpad]: spectrum, then window maxima
+    uint32_t* sX = (uint32_t*)(sP + ca.kpad);       // [kXWords]: histograms, then codes ...
+    uint8_t* sCode = (uint8_t*)sX;                  // [kCodeBytes] one code per bin
+    uint16_t* sList = (uint16_t*)((char*)sX + kListOff);  // [kListCap] candidates / queue
+    float* sBand = (float*)((char*)sX + kBandOff);  // [256] band values in rank order
     __shared__ double red[kFT / kWave];
     __shared__ uint32_t scr[2 * kFT / kWave];
     __shared__ Loc l1lo, l1hi, l2lo, l2hi;
@@ -436,10 +445,10 @@ __global__ __launch_bounds__(kFT) void k_comb_fast(const float* __restrict__ pow
     const int32_t u = blockIdx.x;
     if (u >= n_active || (n_dev && u >= *n_dev)) return;
     const float* row = power + (int64_t)u * K;
-    uint32_t* hA = sW;
-    uint32_t* hB = sW + kHistWords;
-    const int k0 = tid * kFastItems;       // first bin of this thread's segment
-    const int s0 = tid * (kFastItems + 1); // its padded LDS index
+    uint32_t* h2lo = sX;
+    uint32_t* h2hi = sX + kXWords / 2;
+    const int k0 = tid * kFastItems;        // first bin of this thread's segment
+    const int s0 = tid * (kFastItems + 1);  // its padded LDS index
 
     // ---- coalesced load, transpose through LDS ------------------------------
     {
@@ -450,7 +459,7 @@ __global__ __launch_bounds__(kFT) void k_comb_fast(const float* __restrict__ pow
             g[i] = k < K ? row[k] : 0.0f;
         }
 #pragma unroll
-        for (int i = 0; i < 2 * kHistWords / kFT; ++i) sW[tid + i * kFT] = 0u;
+        for (int i = 0; i < kXWords / kFT; ++i) sX[tid + i * kFT] = 0u;
         if (tid == 0) {
             l1lo = l1hi = l2lo = l2hi = Loc{0, 0};
             s_nlist = 0;
@@ -474,19 +483,18 @@ __global__ __launch_bounds__(kFT) void k_comb_fast(const float* __restrict__ pow
     for (int j = 0; j < kFastItems; ++j) {
         if (j < nmine) {
             fsum += v[j];
-            const uint32_t d1 = (__float_as_uint(v[j]) >> 20) & 0x7FFu;
-            atomicAdd(&hA[d1 + (d1 >> 3)], 1u);
+            atomicAdd(&sX[pad8((int)((__float_as_uint(v[j]) >> 20) & 0x7FFu))], 1u);
         }
     }
     const double sum = block_sum_d<kFT>((double)fsum, red);
     const double mean = sum / (double)K;
     const float floor_v = (float)(ca.eps * mean);
-    locate2048x2<true>(hA, 0, ca.b_lo, &l1lo, hA, 0, ca.b_hi, &l1hi, scr);
+    locate_x2<kH1, true>(sX, 0, ca.b_lo, &l1lo, sX, 0, ca.b_hi, &l1hi, scr);
     const uint32_t d1lo = (uint32_t)l1lo.d, d1hi = (uint32_t)l1hi.d;
 #pragma unroll
-    for (int i = 0; i < 2 * kHistWords / kFT; ++i) sW[tid + i * kFT] = 0u;
+    for (int i = 0; i < kXWords / kFT; ++i) sX[tid + i * kFT] = 0u;
     __syncthreads();
-    // ---- log-sum (Eq. 7) and second digit (bits 9..19) ----------------------
+    // ---- log-sum (Eq. 7) and second digit (bits 10..19) ---------------------
     double sl = 0.0;
 #pragma unroll
     for (int j = 0; j < kFastItems; ++j) {
@@ -494,33 +502,42 @@ __global__ __launch_bounds__(kFT) void k_comb_fast(const float* __restrict__ pow
             sl += (double)__log2f(v[j] > floor_v ? v[j] : floor_v);
             const uint32_t b = __float_as_uint(v[j]);
             const uint32_t d1 = (b >> 20) & 0x7FFu;
-            const uint32_t d2 = (b >> 9) & 0x7FFu;
-            if (d1 == d1lo) atomicAdd(&hA[d2 + (d2 >> 3)], 1u);
-            if (d1 == d1hi) atomicAdd(&hB[d2 + (d2 >> 3)], 1u);
+            const int d2 = pad8((int)((b >> 10) & 0x3FFu));
+            if (d1 == d1lo) atomicAdd(&h2lo[d2], 1u);
+            if (d1 == d1hi) atomicAdd(&h2hi[d2], 1u);
         }
     }
     sl = block_sum_d<kFT>(sl, red);
     if (tid == 0) sf_out[u] = mean > 0.0 ? (float)exp2(sl / (double)K - log2(mean)) : 1.0f;
-    locate2048x2<false>(hA, l1lo.before, ca.b_lo, &l2lo, hB, l1hi.before, ca.b_hi, &l2hi, scr);
-    const uint32_t key_lo = (d1lo << 11) | (uint32_t)l2lo.d;
-    const uint32_t key_hi = (d1hi << 11) | (uint32_t)l2hi.d;
-    const uint32_t below_base = l2lo.before;  // values with a 22-bit key below key_lo
+    locate_x2<kH2, false>(h2lo, l1lo.before, ca.b_lo, &l2lo, h2hi, l1hi.before, ca.b_hi, &l2hi,
+                          scr);
+    const uint32_t key_lo = (d1lo << 10) | (uint32_t)l2lo.d;
+    const uint32_t key_hi = (d1hi << 10) | (uint32_t)l2hi.d;
+    const uint32_t below_base = l2lo.before;  // values with a 21-bit key below key_lo
     // ---- classify: below / above / candidate (histograms are dead now) ------
 #pragma unroll
     for (int j = 0; j < kFastItems; ++j) {
         if (j < nmine) {
-            const uint32_t kk = (__float_as_uint(v[j]) >> 9) & 0x3FFFFFu;
-            const uint32_t code = kk < key_lo ? kCodeBelow : (kk > key_hi ? kCodeAbove : kCodeCand);
+            const uint32_t kk = (__float_as_uint(v[j]) >> 10) & 0x1FFFFFu;
+            const uint8_t code = kk < key_lo ? kCodeBelow : (kk > key_hi ? kCodeAbove : kCodeCand);
             if (code == kCodeCand) {
                 const uint32_t pos = atomicAdd(&s_nlist, 1u);
                 if (pos < kListCap) sList[pos] = (uint16_t)(k0 + j);
             }
-            sW[s0 + j] = code;
+            sCode[s0 + j] = code;
         }
     }
     __syncthreads();
     // ---- exact ranks of the candidates by (value, bin) ----------------------
     const int nL = (int)s_nlist;
+    auto set_rank = [&](int ki, float vi, uint32_t r) {
+        const int full = (int)(below_base + r);
+        uint8_t code;
+        if (full < ca.b_lo) code = kCodeBelow;
+        else if (full > ca.b_hi) code = kCodeAbove;
+        else { code = (uint8_t)(full - ca.b_lo); sBand[full - ca.b_lo] = vi; }
+        sCode[padk(ki)] = code;
+    };
     if (nL <= kWave) {
         // one wavefront: candidate b's (value, bin) broadcast by readlane
         if (tid < kWave) {
@@ -533,14 +550,7 @@ __global__ __launch_bounds__(kFT) void k_comb_fast(const float* __restrict__ pow
                 const int kj = __builtin_amdgcn_readlane(ki, b);
                 r += (vj < vi || (vj == vi && kj < ki)) ? 1u : 0u;
             }
-            if (mine) {
-                const int full = (int)(below_base + r);
-                uint32_t code;
-                if (full < ca.b_lo) code = kCodeBelow;
-                else if (full > ca.b_hi) code = kCodeAbove;
-                else { code = (uint32_t)(full - ca.b_lo); sBand[full - ca.b_lo] = vi; }
-                sW[padk(ki)] = code;
-            }
+            if (mine) set_rank(ki, vi, r);
         }
     } else if (nL <= kListCap) {
         for (int a = tid; a < nL; a += kFT) {
@@ -552,363 +562,192 @@ __global__ __launch_bounds__(kFT) void k_comb_fast(const float* __restrict__ pow
                 const float vj = sP[padk(kj)];
                 r += (vj < vi || (vj == vi && kj < ki)) ? 1u : 0u;
             }
-            const int full = (int)(below_base + r);
-            uint32_t code;
-            if (full < ca.b_lo) code = kCodeBelow;
-            else if (full > ca.b_hi) code = kCodeAbove;
-            else { code = (uint32_t)(full - ca.b_lo); sBand[full - ca.b_lo] = vi; }
-            sW[padk(ki)] = code;
+            set_rank(ki, vi, r);
         }
     } else {
         // many exact ties: rank each candidate bin against all candidate bins
 #pragma unroll 1
         for (int j = 0; j < kFastItems; ++j) {
             if (j >= nmine) break;
-            const uint32_t kki = (__float_as_uint(v[j]) >> 9) & 0x3FFFFFu;
+            const uint32_t kki = (__float_as_uint(v[j]) >> 10) & 0x1FFFFFu;
             if (kki < key_lo || kki > key_hi) continue;
             const int ki = k0 + j;
             const float vi = v[j];
             uint32_t r = 0;
             for (int kj = 0; kj < K; ++kj) {
                 const float vj = sP[padk(kj)];
-                const uint32_t kk = (__float_as_uint(vj) >> 9) & 0x3FFFFFu;
+                const uint32_t kk = (__float_as_uint(vj) >> 10) & 0x1FFFFFu;
                 if (kk >= key_lo && kk <= key_hi && (vj < vi || (vj == vi && kj < ki))) ++r;
             }
-            const int full = (int)(below_base + r);
-            uint32_t code;
-            if (full < ca.b_lo) code = kCodeBelow;
-            else if (full > ca.b_hi) code = kCodeAbove;
-            else { code = (uint32_t)(full - ca.b_lo); sBand[full - ca.b_lo] = vi; }
-            sW[s0 + j] = code;
+            set_rank(ki, vi, r);
         }
     }
-    __syncthreads();
-    // ---- per-centre window maxima and window counts --------------------------
-    // Per bin e = [below] | [in band] << 6 | (band index + 1) << 12 for in-band
-    // bins; a window's sum of e holds its below count (bits 0-5), in-band count
-    // (bits 6-11) and, when exactly one bin is in band, that bin's band index
-    // + 1 (bits 12 and up).  The code word becomes own code | sum << 8, and the
-    // spectrum array the window maxima (windows leaving [0, K) are never read).
+    // ---- window maxima in place of the spectrum ------------------------------
     {
         float wm[kFastItems];
-        uint32_t wc[kFastItems];
         if (DKT >= 0) {
             constexpr int D = DKT >= 0 ? DKT : 0;
             constexpr int NH = kFastItems + 2 * D;
             float hv[NH];
-            uint32_t cum[NH], own[kFastItems];
-            uint32_t run = 0;
 #pragma unroll
             for (int q = 0; q < NH; ++q) {
                 const int o = q - D;  // offset from k0
                 const int k = k0 + o;
                 const int pidx = s0 + o + (o < 0 ? -1 : (o >= kFastItems ? 1 : 0));
-                const bool in = k >= 0 && k < K;
-                hv[q] = (o >= 0 && o < kFastItems) ? v[o] : (in ? sP[pidx] : 0.0f);
-                const uint32_t c = in ? sW[pidx] : kCodeAbove;
-                if (o >= 0 && o < kFastItems) own[o] = c;
-                run += c == kCodeBelow ? 1u : (c < kCodeCand ? (0x40u | ((c + 1u) << 12)) : 0u);
-                cum[q] = run;
+                hv[q] = (o >= 0 && o < kFastItems) ? v[o]
+                        : ((k >= 0 && k < K) ? sP[pidx] : 0.0f);
             }
 #pragma unroll
             for (int j = 0; j < kFastItems; ++j) {
                 float mx = hv[j];
 #pragma unroll
                 for (int q = 1; q <= 2 * D; ++q) mx = fmaxf(mx, hv[j + q]);
-                const uint32_t sm = cum[j + 2 * D] - (j > 0 ? cum[j - 1] : 0u);
                 wm[j] = mx;
-                wc[j] = own[j] | (sm << 8);
             }
         } else {
 #pragma unroll
             for (int j = 0; j < kFastItems; ++j) {
                 const int k = k0 + j;
                 float mx = 0.0f;
-                uint32_t sm = 0, own = kCodeAbove;
-                if (k < K) {
-                    own = sW[s0 + j];
-                    if (k >= dk && k + dk <= K - 1) {
-                        mx = sP[padk(k - dk)];
-                        for (int q = -dk; q <= dk; ++q) {
-                            mx = fmaxf(mx, sP[padk(k + q)]);
-                            const uint32_t c = sW[padk(k + q)];
-                            sm += c == kCodeBelow ? 1u
-                                : (c < kCodeCand ? (0x40u | ((c + 1u) << 12)) : 0u);
-                        }
-                    }
+                if (k >= dk && k + dk <= K - 1) {
+                    mx = sP[padk(k - dk)];
+                    for (int q = -dk + 1; q <= dk; ++q) mx = fmaxf(mx, sP[padk(k + q)]);
                 }
                 wm[j] = mx;
-                wc[j] = own | (sm << 8);
             }
         }
-        __syncthreads();  // every read of the old arrays is done
+        __syncthreads();  // every read of the spectrum is done; codes and band are complete
 #pragma unroll
-        for (int j = 0; j < kFastItems; ++j) {
-            if (j < nmine) {
-                sP[s0 + j] = wm[j];
-                sW[s0 + j] = wc[j];
-            }
-        }
+        for (int j = 0; j < kFastItems; ++j)
+            if (j < nmine) sP[s0 + j] = wm[j];
     }
     __syncthreads();
     // ---- candidates (Eq. 8-11) ----------------------------------------------
-    constexpr int MI = MT > 0 ? MT : kInbCap;  // windows whose in-band bin is kept
     const float fden_floor = (float)(ca.eps * mean);
     const int bw = ca.b_hi - ca.b_lo;
     float best = 0.0f;
     int best_i = -1;
-    // Complement median's band index by a scan of the distinct window bins'
-    // own codes (overlapping windows, or windows with several in-band bins).
-    auto scan_q = [&](auto&& centre, int mv, int& hsize) -> int {
-        int below = 0;
-        hsize = 0;
-        int ph = -1;
-        for (int m = 1; m <= mv; ++m) {
-            const int cm = centre(m);
-            const int lo = (cm - dk) > ph + 1 ? (cm - dk) : ph + 1;
-            for (int k = lo; k <= cm + dk; ++k) {
-                ++hsize;
-                below += (sW[padk(k)] & 0xFFu) == kCodeBelow ? 1 : 0;
-            }
-            ph = cm + dk;
+    auto centre_of = [&](int i, int m) -> int {
+        if (ca.g >= 0) return m * ((int)ca.g + i) - (int)ca.g;
+        const double num = (double)(m - 1) * (double)ca.f0 + (double)m * (double)i * (double)ca.df;
+        return (int)floor(num / (double)ca.df + 0.5);
+    };
+    // harmonics whose window stays inside [0, K)
+    auto n_valid = [&](int i) -> int {
+        int mv = 0;
+#pragma unroll
+        for (int m = 1; m <= (MT > 0 ? MT : 32); ++m) {
+            if (m > M || centre_of(i, m) + dk > K - 1) break;
+            mv = m;
         }
-        const int t = (K - hsize - 1) / 2 + below - ca.b_lo;
-        int q = t;
-        const int hmax = M * (2 * dk + 1);
-        for (int iter = 0; iter <= hmax + 1; ++iter) {
-            int extra = 0;
-            ph = -1;
+        return mv;
+    };
+    // exact score of candidate i from its window maxima and window bins' codes
+    auto eval_exact = [&](int i) {
+        const int mv = n_valid(i);
+        float snr = 0.0f;
+        if (mv >= ca.h_min) {
+            float smax = 0.0f;
+            int below = 0, hsize = 0, nin = 0;
+            bool spill = false;
+            int inr[kInbCap];
+            int ph = -1;
             for (int m = 1; m <= mv; ++m) {
-                const int cm = centre(m);
+                const int cm = centre_of(i, m);
+                smax += sP[padk(cm)];
                 const int lo = (cm - dk) > ph + 1 ? (cm - dk) : ph + 1;
                 for (int k = lo; k <= cm + dk; ++k) {
-                    const uint32_t c = sW[padk(k)] & 0xFFu;
-                    if (c < kCodeCand && (int)c <= q) ++extra;
+                    const uint8_t c = sCode[padk(k)];
+                    ++hsize;
+                    if (c == kCodeBelow) ++below;
+                    else if (c < kCodeCand) {
+                        if (nin < kInbCap) inr[nin++] = (int)c;
+                        else spill = true;
+                    }
                 }
                 ph = cm + dk;
             }
-            if (t + extra == q) break;
-            q = t + extra;
-        }
-        return q;
-    };
-    auto finish = [&](int i, float smax, int mv, int hsize, int q) {
-        float med = 0.0f;
-        if (K - hsize > 0) {
-            q = q < 0 ? 0 : (q > bw ? bw : q);
-            med = sBand[q];
-        }
-        const float N = smax / (float)mv;
-        const float den = med > fden_floor ? med : fden_floor;
-        const float snr = den > 0.0f ? __fdividef(N, den) : 0.0f;
-        // order-independent: highest score, lowest bin on ties
-        if (best_i < 0 || snr > best || (snr == best && i < best_i)) { best = snr; best_i = i; }
-        return snr;
-    };
-    if (MT > 0 && ca.g >= 0) {
-        // integer grid ratio g = f0 / df: centres c_m = m (g + i) - g, equally spaced
-        const int g = (int)ca.g;
-        const int wlen = 2 * dk + 1;
-        auto nvalid = [&](int step) {
-            int mv = 0;
-#pragma unroll
-            for (int m = 1; m <= MI; ++m) mv += (m * step - g + dk <= K - 1) ? 1 : 0;
-            return mv;
-        };
-        // candidates with overlapping windows, or a window holding several
-        // in-band bins: fixed point over those windows' bins (or a full scan)
-        auto eval_slow = [&](int i) {
-            const int step = g + i;
-            const int mv = nvalid(step);
-            float smax = 0.0f;
-            int below = 0;
-            int hsize = mv * wlen;
-            int q;
-            if (step <= 2 * dk) {
-#pragma unroll
-                for (int m = 1; m <= MI; ++m)
-                    if (m <= mv) smax += sP[padk(m * step - g)];
-                auto centre = [&](int m) -> int { return m * step - g; };
-                q = scan_q(centre, mv, hsize);
-            } else {
-#pragma unroll
-                for (int m = 1; m <= MI; ++m)
-                    if (m <= mv) {
-                        const int a = padk(m * step - g);
-                        smax += sP[a];
-                        below += (int)((sW[a] >> 8) & 0x3Fu);
-                    }
-                const int t = (K - hsize - 1) / 2 + below - ca.b_lo;
-                q = t;
-                for (int iter = 0; iter <= hsize; ++iter) {
-                    int extra = 0;
+            // band index of the median: smallest q with q = t + #(window band indices <= q)
+            const int t = (K - hsize - 1) / 2 + below - ca.b_lo;
+            int q = t;
+            for (int iter = 0; iter <= hsize; ++iter) {
+                int extra = 0;
+                if (!spill) {
+                    for (int j = 0; j < nin; ++j) extra += inr[j] <= q ? 1 : 0;
+                } else {
+                    int p2 = -1;
                     for (int m = 1; m <= mv; ++m) {
-                        const int cm = m * step - g;
-                        for (int k = cm - dk; k <= cm + dk; ++k) {
-                            const uint32_t c = sW[padk(k)] & 0xFFu;
+                        const int cm = centre_of(i, m);
+                        const int lo = (cm - dk) > p2 + 1 ? (cm - dk) : p2 + 1;
+                        for (int k = lo; k <= cm + dk; ++k) {
+                            const uint8_t c = sCode[padk(k)];
                             extra += (c < kCodeCand && (int)c <= q) ? 1 : 0;
                         }
-                    }
-                    if (t + extra == q) break;
-                    q = t + extra;
-                }
-            }
-            const float snr = finish(i, smax, mv, hsize, q);
-            if (snr_all) snr_all[(int64_t)u * K + i] = snr;
-        };
-        // exact score of one candidate; updates this thread's best
-        auto eval_fast = [&](int i) {
-            const int step = g + i;
-            const int mv = nvalid(step);
-            float snr = 0.0f;
-            if (mv >= ca.h_min) {
-                float smax = 0.0f;
-                int below = 0;
-                bool slow = step <= 2 * dk;  // windows overlap
-                int inr[MI];
-#pragma unroll
-                for (int m = 1; m <= MI; ++m) {
-                    const bool val = m <= mv;
-                    const int cm = val ? m * step - g : dk;
-                    const int a = padk(cm);
-                    const float wmx = sP[a];
-                    const uint32_t w = sW[a];
-                    const uint32_t wi = val ? (w >> 14) & 0x3Fu : 0u;
-                    smax += val ? wmx : 0.0f;
-                    below += val ? (int)((w >> 8) & 0x3Fu) : 0;
-                    inr[m - 1] = wi == 1u ? (int)((w >> 20) & 0xFFFu) - 1 : 0x7FFF;
-                    slow = slow || wi > 1u;
-                }
-                if (slow) {
-                    eval_slow(i);
-                    return;
-                }
-                const int hsize = mv * wlen;
-                // q = t + #(inr <= q): walk the window band indices in ascending order
-#pragma unroll
-                for (int a = 0; a < MI; ++a)
-#pragma unroll
-                    for (int b = a + 1; b < MI; ++b) {
-                        const int lo = min(inr[a], inr[b]);
-                        const int hi = max(inr[a], inr[b]);
-                        inr[a] = lo;
-                        inr[b] = hi;
-                    }
-                int q = (K - hsize - 1) / 2 + below - ca.b_lo;
-#pragma unroll
-                for (int a = 0; a < MI; ++a) q += inr[a] <= q ? 1 : 0;
-                snr = finish(i, smax, mv, hsize, q);
-            }
-            if (snr_all) snr_all[(int64_t)u * K + i] = snr;
-        };
-        // Every candidate's median lies in [sBand[0], sBand[bw]], so its score
-        // lies in [N / den_hi, N / den_lo].  Only candidates whose upper bound
-        // reaches the largest lower bound can be the argmax; the others need no
-        // median (unless every score is requested).
-        const float den_lo = fmaxf(sBand[0], fden_floor);
-        const float den_hi = fmaxf(sBand[bw], fden_floor);
-        if (snr_all == nullptr && den_lo > 0.0f) {
-            constexpr int kIt = 4096 / kFT;  // candidate rounds per thread, i < K <= 4096
-            float nv[kIt];
-            float lb = 0.0f;
-            const float r_hi = 1.0f / den_hi, r_lo = 1.0f / den_lo;
-#pragma unroll
-            for (int r = 0; r < kIt; ++r) {
-                const int i = dk + tid + r * kFT;
-                nv[r] = -1.0f;
-                if (i <= i_max) {
-                    const int step = g + i;
-                    const int mv = nvalid(step);
-                    if (mv >= ca.h_min) {
-                        float smax = 0.0f;
-#pragma unroll
-                        for (int m = 1; m <= MI; ++m) {
-                            const bool val = m <= mv;
-                            const float wmx = sP[padk(val ? m * step - g : dk)];
-                            smax += val ? wmx : 0.0f;
-                        }
-                        nv[r] = smax / (float)mv;  // the N of the exact evaluation
-                        lb = fmaxf(lb, nv[r] * r_hi);
+                        p2 = cm + dk;
                     }
                 }
+                if (t + extra == q) break;
+                q = t + extra;
             }
-#pragma unroll
-            for (int d = 32; d >= 1; d >>= 1) lb = fmaxf(lb, __shfl_xor(lb, d, 64));
-            if (__lane_id() == 0) s_best[tid / kWave] = lb;
-            __syncthreads();
-            float thr = 0.0f;
-#pragma unroll
-            for (int q = 0; q < kFT / kWave; ++q) thr = fmaxf(thr, s_best[q]);
-            thr *= 0.999f;  // margin over the rounding of both bounds
-#pragma unroll
-            for (int r = 0; r < kIt; ++r) {
-                if (nv[r] >= 0.0f && nv[r] * r_lo >= thr) {
-                    const int i = dk + tid + r * kFT;
-                    const uint32_t pos = atomicAdd(&s_qn, 1u);
-                    if (pos < kListCap) sList[pos] = (uint16_t)i;
-                    else eval_fast(i);
-                }
+            float med = 0.0f;
+            if (K - hsize > 0) {
+                q = q < 0 ? 0 : (q > bw ? bw : q);
+                med = sBand[q];
             }
-            __syncthreads();
-            const int nq = (int)(s_qn < (uint32_t)kListCap ? s_qn : (uint32_t)kListCap);
-            for (int e = tid; e < nq; e += kFT) eval_fast((int)sList[e]);
-            __syncthreads();  // s_best is reused by the final reduction
-        } else {
-            for (int i = dk + tid; i <= i_max; i += kFT) eval_fast(i);
+            const float N = smax / (float)mv;
+            const float den = med > fden_floor ? med : fden_floor;
+            snr = den > 0.0f ? __fdividef(N, den) : 0.0f;
+            // order-independent: highest score, lowest bin on ties
+            if (best_i < 0 || snr > best || (snr == best && i < best_i)) { best = snr; best_i = i; }
         }
-    } else {
-        for (int i = dk + tid; i <= i_max; i += kFT) {
-            auto centre = [&](int m) -> int {
-                if (ca.g >= 0) return (m - 1) * (int)ca.g + m * i;
-                const double num =
-                    (double)(m - 1) * (double)ca.f0 + (double)m * (double)i * (double)ca.df;
-                return (int)floor(num / (double)ca.df + 0.5);
-            };
+        if (snr_all) snr_all[(int64_t)u * K + i] = snr;
+    };
+    // Every candidate's median lies in [band[0], band[bw]], so its score lies in
+    // [N / den_hi, N / den_lo]: only candidates whose upper bound reaches the
+    // largest lower bound can be the argmax.
+    const float den_lo = fmaxf(sBand[0], fden_floor);
+    const float den_hi = fmaxf(sBand[bw], fden_floor);
+    if (snr_all == nullptr && den_lo > 0.0f) {
+        const float r_hi = 1.0f / den_hi, r_lo = 1.0f / den_lo;
+        // N of candidate i (the value the exact evaluation uses), -1 if inadmissible
+        auto n_of = [&](int i) -> float {
             int mv = 0;
-            bool slow = false;
-            int prev_c = -1;
-            for (int m = 1; m <= M; ++m) {
-                const int cm = centre(m);
-                if (cm + dk > K - 1) break;
-                if (m > 1 && cm - prev_c <= 2 * dk) slow = true;
-                prev_c = cm;
-                mv = m;
-            }
-            float snr = 0.0f;
-            if (mv >= ca.h_min) {
-                float smax = 0.0f;
-                int below = 0;
-                int inr[kInbCap];
+            float smax = 0.0f;
 #pragma unroll
-                for (int j = 0; j < kInbCap; ++j) inr[j] = 0x7FFF;
-                for (int m = 1; m <= mv; ++m) {
-                    const int cm = centre(m);
-                    smax += sP[padk(cm)];
-                    const uint32_t w = sW[padk(cm)];
-                    below += (int)((w >> 8) & 0x3Fu);
-                    const uint32_t wi = (w >> 14) & 0x3Fu;
-                    if (wi == 1u && m <= kInbCap) inr[m - 1] = (int)((w >> 20) & 0xFFFu) - 1;
-                    else if (wi != 0u) slow = true;
-                }
-                int hsize = mv * (2 * dk + 1);
-                int q;
-                if (!slow) {
-                    const int t = (K - hsize - 1) / 2 + below - ca.b_lo;
-                    q = t;
-                    for (int iter = 0; iter <= kInbCap; ++iter) {
-                        int extra = 0;
-#pragma unroll
-                        for (int j = 0; j < kInbCap; ++j) extra += inr[j] <= q ? 1 : 0;
-                        if (t + extra == q) break;
-                        q = t + extra;
-                    }
-                } else {
-                    q = scan_q(centre, mv, hsize);
-                }
-                snr = finish(i, smax, mv, hsize, q);
+            for (int m = 1; m <= (MT > 0 ? MT : 32); ++m) {
+                if (m > M) break;
+                const int cm = centre_of(i, m);
+                const bool val = cm + dk <= K - 1 && mv == m - 1;
+                const float wmx = sP[padk(val ? cm : dk)];
+                smax += val ? wmx : 0.0f;
+                mv += val ? 1 : 0;
             }
-            if (snr_all) snr_all[(int64_t)u * K + i] = snr;
+            return mv >= ca.h_min ? smax / (float)mv : -1.0f;
+        };
+        float lb = 0.0f;
+        for (int i = dk + tid; i <= i_max; i += kFT) lb = fmaxf(lb, n_of(i) * r_hi);
+#pragma unroll
+        for (int d = 32; d >= 1; d >>= 1) lb = fmaxf(lb, __shfl_xor(lb, d, 64));
+        if (__lane_id() == 0) s_best[tid / kWave] = lb;
+        __syncthreads();
+        float thr = 0.0f;
+#pragma unroll
+        for (int q = 0; q < kFT / kWave; ++q) thr = fmaxf(thr, s_best[q]);
+        thr *= 0.999f;  // margin over the rounding of both bounds
+        for (int i = dk + tid; i <= i_max; i += kFT) {
+            const float n = n_of(i);
+            if (n >= 0.0f && n * r_lo >= thr) {
+                const uint32_t pos = atomicAdd(&s_qn, 1u);
+                if (pos < kListCap) sList[pos] = (uint16_t)i;
+                else eval_exact(i);
+            }
         }
+        __syncthreads();
+        const int nq = (int)(s_qn < (uint32_t)kListCap ? s_qn : (uint32_t)kListCap);
+        for (int e = tid; e < nq; e += kFT) eval_exact((int)sList[e]);
+        __syncthreads();  // s_best is reused by the final reduction
+    } else {
+        for (int i = dk + tid; i <= i_max; i += kFT) eval_exact(i);
     }
     if (snr_all) {
         for (int i = tid; i < K; i += kFT)
@@ -996,7 +835,7 @@ int comb_run(const float* power, int32_t n_active, const int32_t* n_dev, const d
     if (ca.K <= 4096 && bw <= 253) {
         CombArgs cf = ca;
         cf.kpad = ((ca.K - 1) + ((ca.K - 1) >> kSegShift) + 1 + 3) / 4 * 4;  // padded bin array
-        const size_t lds = (size_t)cf.kpad * 4 + (size_t)2 * kHistWords * 4;
+        const size_t lds = (size_t)cf.kpad * 4 + (size_t)kXWords * 4;
         const dim3 gr((unsigned)n_active), bl(kFT);
         if (ca.M == 4 && ca.dk == 3)
             hipLaunchKernelGGL((k_comb_fast<4, 3>), gr, bl, lds, s, power, n_active, cf, i_max, sf,
