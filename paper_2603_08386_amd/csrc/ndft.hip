@@ -5,10 +5,11 @@
 // owns the bins j = tile_base + l + 64 m, m < BPL, and keeps their complex
 // sums in registers.  The pixel's events are staged 64 at a time in LDS
 // together with their exact per-event residues
-//     A = (f_tile t) mod Q,   D = (df t) mod Q,   S = (64 D) mod Q,
-// and the step phasor w = exp(i 2 pi S / Q) (FP64 sin/cos, rounded to FP32).
-// For each event every lane forms its exact anchor residue (A + l D) mod Q,
-// one FP32 sin/cos, and then walks its BPL bins by complex rotation with w.
+//     A = (f_tile t) mod Q,   D = (df t) mod Q
+// as fixed-point fractions of a revolution, and the step phasor
+// w = exp(i 2 pi 64 D / Q).  For each event every lane forms its anchor phase
+// (A + l D) / Q in fixed point, one FP32 sin/cos, and then walks its BPL bins
+// by complex rotation with w.
 //
 // Launch forms.  Work is a list of units (pixel, bin tile, event range):
 //   plain       one wavefront per (pixel, tile), units implied by blockIdx;
@@ -26,7 +27,9 @@ struct GridDev {
     int64_t f0, df;
     int32_t K;
     uint32_t Q;
-    double invQ;
+    double invQ;  // 1 / Q
+    double q32;   // 2^32 / Q
+    double q48;   // 2^48 / Q
 };
 
 static bool grid_ok(const ddhf_grid_t* g) {
@@ -46,6 +49,8 @@ static GridDev grid_dev(const ddhf_grid_t* g) {
     d.K = g->K;
     d.Q = g->mode == DDHF_GRID_HZ ? 1000000000u : (uint32_t)g->T_w_us;
     d.invQ = 1.0 / (double)d.Q;
+    d.q32 = 4294967296.0 / (double)d.Q;
+    d.q48 = 281474976710656.0 / (double)d.Q;
     return d;
 }
 
@@ -56,21 +61,34 @@ static GridDev grid_dev(const ddhf_grid_t* g) {
 // and q2 = F & 0xFFFF.  The phase of bin offset m is then the 32-bit value
 //     phi = phiA + m q1 + ((m q2) >> 16)   (mod 2^32),
 // formed with 24-bit integer multiply-adds; for m < 2^10 its error is below
-// 2^-31 revolutions.
+// 2^-31 revolutions.  The fractions come from FP64 products with 2^32 / Q and
+// 2^48 / Q, which may be one unit off the exact floor (2^-32 and 2^-48
+// revolutions): far below FP32 resolution.
 // ---------------------------------------------------------------------------
 struct Frac {
     uint32_t phiA, q1lo, q1hi, q2;
+    uint64_t F;  // 48-bit fraction of D
 };
 
-__device__ __forceinline__ Frac make_frac(uint32_t A, uint32_t D, uint32_t Q) {
+// x mod Q for 0 <= x < 2^63.  The FP64 quotient is off by at most one: x is
+// rounded by at most 2^10 only when x >= 2^53, and then Q = 10^9 (Hz grid);
+// on the mode grid x < 2^43 is exact.  One exact integer correction each way.
+__device__ __forceinline__ uint32_t mod_q(uint64_t x, const GridDev& g) {
+    const uint64_t q = (uint64_t)((double)x * g.invQ);
+    int64_t r = (int64_t)(x - q * (uint64_t)g.Q);
+    r += r < 0 ? (int64_t)g.Q : 0;
+    r -= r >= (int64_t)g.Q ? (int64_t)g.Q : 0;
+    return (uint32_t)r;
+}
+
+__device__ __forceinline__ Frac make_frac(uint32_t A, uint32_t D, const GridDev& g) {
     Frac f;
-    f.phiA = (uint32_t)(((uint64_t)A << 32) / Q);
-    const uint64_t xd = (uint64_t)D << 32;
-    const uint32_t q1 = (uint32_t)(xd / Q);
-    const uint64_t r1 = xd % Q;
+    f.phiA = (uint32_t)((double)A * g.q32);
+    f.F = (uint64_t)((double)D * g.q48);
+    const uint32_t q1 = (uint32_t)(f.F >> 16);
     f.q1lo = q1 & 0xFFFFu;
     f.q1hi = q1 >> 16;
-    f.q2 = (uint32_t)((r1 << 16) / Q);
+    f.q2 = (uint32_t)(f.F & 0xFFFFu);
     return f;
 }
 
@@ -166,7 +184,7 @@ struct EvStage {
 
 // Stages events [c0, c0 + 64) of a unit: exact residues A = f_tile t mod Q and
 // D = df t mod Q as fixed-point fractions, and the step phasor
-// exp(2 pi i (step_mul D mod Q) / Q) from the exact residue in FP64.
+// exp(i 2 pi step_mul D / Q) from the 48-bit fraction of D.
 __device__ __forceinline__ void stage_event(EvStage* st, int lane, int32_t c0, int32_t end,
                                             const uint32_t* t_rel, const float* av,
                                             uint64_t f_tile, const GridDev& g, uint32_t step_mul) {
@@ -174,21 +192,16 @@ __device__ __forceinline__ void stage_event(EvStage* st, int lane, int32_t c0, i
     if (e < end) {
         const uint64_t t = t_rel[e];
         EvStage s;
-        const uint32_t A = (uint32_t)((f_tile * t) % g.Q);
-        const uint32_t D = (uint32_t)(((uint64_t)g.df * t) % g.Q);
-        const Frac f = make_frac(A, D, g.Q);
+        const uint32_t A = mod_q(f_tile * t, g);
+        const uint32_t D = mod_q((uint64_t)g.df * t, g);
+        const Frac f = make_frac(A, D, g);
         s.phiA = f.phiA;
         s.q1lo = f.q1lo;
         s.q1hi = f.q1hi;
         s.q2 = f.q2;
         s.pad = 0.0f;
-        const uint32_t S = (uint32_t)(((uint64_t)D * step_mul) % g.Q);
-        double rs = (double)S * g.invQ;
-        if (rs >= 0.5) rs -= 1.0;
-        double sn, cs;
-        sincospi(2.0 * rs, &sn, &cs);
-        s.wc = (float)cs;
-        s.ws = (float)sn;
+        // step phasor exp(2 pi i step_mul D / Q) from the 48-bit fraction
+        sincos_fixed((uint32_t)((f.F * step_mul) >> 16), s.ws, s.wc);
         s.a = av[e];
         st[lane] = s;
     }
@@ -260,6 +273,33 @@ __global__ __launch_bounds__(64) void k_ndft_valu(const int32_t* __restrict__ ro
 // Accumulator layout (32x32 block): element r of lane l is row
 // 8 (r / 4) + 4 (l / 32) + r % 4, column l % 32.
 // ---------------------------------------------------------------------------
+// MFMA operands of one event.  Lower lanes hold U(row) = a (c, s), upper lanes
+// V(col) = (c, s).  v_permlane32_swap(x, y) returns lo = [x(0..31), y(0..31)]
+// and hi = [x(32..63), y(32..63)]: one instruction moves a value across the
+// two halves of the wave.
+struct MfOps {
+    float aop, bre, bim, uc, us, wc, ws;
+};
+
+__device__ __forceinline__ MfOps mf_operands(const EvStage& s, bool upper, uint32_t m) {
+    float sn, cs;
+    sincos_fixed(frac_phase(upper ? 0u : s.phiA, s.q1lo, s.q1hi, s.q2, m), sn, cs);
+    const float w = upper ? 1.0f : s.a;
+    MfOps o;
+    o.uc = cs * w;
+    o.us = sn * w;
+    const auto p1 = __builtin_amdgcn_permlane32_swap(__float_as_uint(o.uc),
+                                                     __float_as_uint(o.us), false, false);
+    const auto p2 = __builtin_amdgcn_permlane32_swap(__float_as_uint(o.us),
+                                                     __float_as_uint(o.us), false, false);
+    o.aop = upper ? __uint_as_float(p1[0]) : o.uc;   // A: Re U | Im U (lower's s)
+    o.bre = upper ? -o.us : __uint_as_float(p1[1]);  // B real: Re V (upper's c) | -Im V
+    o.bim = upper ? o.uc : __uint_as_float(p2[1]);   // B imag: Im V (upper's s) | Re V
+    o.wc = s.wc;
+    o.ws = s.ws;
+    return o;
+}
+
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 
 template <int NB, int MODE>
@@ -290,31 +330,29 @@ __global__ __launch_bounds__(64, 2) void k_ndft_mfma(const int32_t* __restrict__
             stage_event(st, lane, c0, un.end, t_rel, av, f_tile, g, 1024u);
             __syncthreads();
             const int ne = (un.end - c0) < 64 ? (un.end - c0) : 64;
+            // software pipelined: the next event's phasors are formed while this
+            // event's MFMAs run (no branch inside the body, so they interleave)
+            MfOps o = mf_operands(st[0], upper, m);
             for (int k = 0; k < ne; ++k) {
-                const EvStage s = st[k];
-                float sn, cs;
-                sincos_fixed(frac_phase(upper ? 0u : s.phiA, s.q1lo, s.q1hi, s.q2, m), sn, cs);
-                const float w = upper ? 1.0f : s.a;
-                float uc = cs * w, us = sn * w;            // lower: U; upper: V
-                const float x1 = __shfl_xor(upper ? uc : us, 32, 64);  // lower gets Re V, upper Im U
-                const float x2 = __shfl_xor(us, 32, 64);                // lower gets Im V
-                float aop = upper ? x1 : uc;
-                const float bre = upper ? -us : x1;
-                const float bim = upper ? uc : x2;
+                const EvStage sn = st[k + 1 < ne ? k + 1 : k];
+                float aop = o.aop, uc = o.uc, us = o.us;
+                const float bre = o.bre, bim = o.bim, wc = o.wc, ws = o.ws;
 #pragma unroll
                 for (int b = 0; b < NB; ++b) {
                     cre[b] = __builtin_amdgcn_mfma_f32_32x32x2f32(aop, bre, cre[b], 0, 0, 0);
                     cim[b] = __builtin_amdgcn_mfma_f32_32x32x2f32(aop, bim, cim[b], 0, 0, 0);
                     if (b + 1 < NB) {
-                        // next 32-row tile of U: multiply by the exact step phasor
-                        const float nr = uc * s.wc - us * s.ws;
-                        const float ni = uc * s.ws + us * s.wc;
+                        // next 32-row tile of U: multiply by the step phasor
+                        const float nr = uc * wc - us * ws;
+                        const float ni = uc * ws + us * wc;
                         uc = nr;
                         us = ni;
-                        const float xu = __shfl_xor(us, 32, 64);
-                        aop = upper ? xu : uc;
+                        const auto p = __builtin_amdgcn_permlane32_swap(
+                            __float_as_uint(us), __float_as_uint(us), false, false);
+                        aop = upper ? __uint_as_float(p[0]) : uc;
                     }
                 }
+                o = mf_operands(sn, upper, m);
             }
             __syncthreads();
         }
