@@ -60,7 +60,7 @@ static GridDev grid_dev(const ddhf_grid_t* g) {
 // fraction F = floor(D 2^48 / Q) held as q1 = F >> 16 (split in 16-bit halves)
 // and q2 = F & 0xFFFF.  The phase of bin offset m is then the 32-bit value
 //     phi = phiA + m q1 + ((m q2) >> 16)   (mod 2^32),
-// formed with 24-bit integer multiply-adds; for m < 2^10 its error is below
+// formed with 24-bit integer multiply-adds; for m < 2^11 its error is below
 // 2^-31 revolutions.  The fractions come from FP64 products with 2^32 / Q and
 // 2^48 / Q, which may be one unit off the exact floor (2^-32 and 2^-48
 // revolutions): far below FP32 resolution.
@@ -94,8 +94,8 @@ __device__ __forceinline__ Frac make_frac(uint32_t A, uint32_t D, const GridDev&
 
 __device__ __forceinline__ uint32_t frac_phase(uint32_t phiA, uint32_t q1lo, uint32_t q1hi,
                                                uint32_t q2, uint32_t m) {
-    // operands below 2^16 and 2^10: the products map onto 24-bit multiply-adds
-    const uint32_t mm = m & 0x3FFu;
+    // operands below 2^16 and 2^11: the products map onto 24-bit multiply-adds
+    const uint32_t mm = m & 0x7FFu;
     const uint32_t t = mm * (q1lo & 0xFFFFu) + phiA;
     const uint32_t u = mm * (q1hi & 0xFFFFu);
     const uint32_t v = mm * (q2 & 0xFFFFu);
@@ -123,6 +123,15 @@ __device__ __forceinline__ void sincos_fixed(uint32_t phi, float& s, float& c) {
     const float ac = (q & 1u) ? sv : cv;
     s = (q & 2u) ? -as : as;
     c = ((q + 1u) & 2u) ? -ac : ac;
+}
+
+// sin, cos of 2 pi phi / 2^32 on the transcendental unit (v_sin_f32 and
+// v_cos_f32 take their argument in revolutions); the argument is the signed
+// fraction in [-1/2, 1/2), rounded to FP32.
+__device__ __forceinline__ void sincos_rev(uint32_t phi, float& s, float& c) {
+    const float x = (float)(int32_t)phi * 2.3283064365386963e-10f;  // 2^-32
+    s = __builtin_amdgcn_sinf(x);
+    c = __builtin_amdgcn_cosf(x);
 }
 
 struct Unit {
@@ -231,7 +240,7 @@ __global__ __launch_bounds__(64) void k_ndft_valu(const int32_t* __restrict__ ro
             for (int k = 0; k < ne; ++k) {
                 const EvStage s = st[k];
                 float c, sn;
-                sincos_fixed(frac_phase(s.phiA, s.q1lo, s.q1hi, s.q2, (uint32_t)lane), sn, c);
+                sincos_rev(frac_phase(s.phiA, s.q1lo, s.q1hi, s.q2, (uint32_t)lane), sn, c);
                 float zr = s.a * c, zi = s.a * sn;
 #pragma unroll
                 for (int m = 0; m < BPL; ++m) {
@@ -273,28 +282,30 @@ __global__ __launch_bounds__(64) void k_ndft_valu(const int32_t* __restrict__ ro
 // Accumulator layout (32x32 block): element r of lane l is row
 // 8 (r / 4) + 4 (l / 32) + r % 4, column l % 32.
 // ---------------------------------------------------------------------------
-// MFMA operands of one event.  Lower lanes hold U(row) = a (c, s), upper lanes
-// V(col) = (c, s).  v_permlane32_swap(x, y) returns lo = [x(0..31), y(0..31)]
-// and hi = [x(32..63), y(32..63)]: one instruction moves a value across the
-// two halves of the wave.
+// MFMA operands of one event.  Every lane forms V(col = lane mod 32) (both
+// halves, so the B operands need no exchange) and one U row: row lane of the
+// tile pair (0, 1), i.e. phase offset 32 lane bins.  v_permlane32_swap(c, s)
+// returns lo = [c(0..31), s(0..31)] and hi = [c(32..63), s(32..63)], which are
+// exactly the A operands (Re U | Im U of each row) of tiles 0 and 1.  Tiles 2
+// and 3 follow by one rotation with the step phasor exp(i 2 pi 2048 D / Q).
 struct MfOps {
-    float aop, bre, bim, uc, us, wc, ws;
+    float a0, a1, bre, bim, uc, us, wc, ws;
 };
 
-__device__ __forceinline__ MfOps mf_operands(const EvStage& s, bool upper, uint32_t m) {
-    float sn, cs;
-    sincos_fixed(frac_phase(upper ? 0u : s.phiA, s.q1lo, s.q1hi, s.q2, m), sn, cs);
-    const float w = upper ? 1.0f : s.a;
+__device__ __forceinline__ MfOps mf_operands(const EvStage& s, bool upper, uint32_t mU,
+                                             uint32_t mV) {
+    float vs, vc, sn, cs;
+    sincos_rev(frac_phase(0u, s.q1lo, s.q1hi, s.q2, mV), vs, vc);
+    sincos_rev(frac_phase(s.phiA, s.q1lo, s.q1hi, s.q2, mU), sn, cs);
     MfOps o;
-    o.uc = cs * w;
-    o.us = sn * w;
-    const auto p1 = __builtin_amdgcn_permlane32_swap(__float_as_uint(o.uc),
-                                                     __float_as_uint(o.us), false, false);
-    const auto p2 = __builtin_amdgcn_permlane32_swap(__float_as_uint(o.us),
-                                                     __float_as_uint(o.us), false, false);
-    o.aop = upper ? __uint_as_float(p1[0]) : o.uc;   // A: Re U | Im U (lower's s)
-    o.bre = upper ? -o.us : __uint_as_float(p1[1]);  // B real: Re V (upper's c) | -Im V
-    o.bim = upper ? o.uc : __uint_as_float(p2[1]);   // B imag: Im V (upper's s) | Re V
+    o.uc = cs * s.a;
+    o.us = sn * s.a;
+    const auto p = __builtin_amdgcn_permlane32_swap(__float_as_uint(o.uc), __float_as_uint(o.us),
+                                                    false, false);
+    o.a0 = __uint_as_float(p[0]);
+    o.a1 = __uint_as_float(p[1]);
+    o.bre = upper ? -vs : vc;  // B real: Re V | -Im V
+    o.bim = upper ? vc : vs;   // B imag: Im V | Re V
     o.wc = s.wc;
     o.ws = s.ws;
     return o;
@@ -309,12 +320,13 @@ __global__ __launch_bounds__(64, 2) void k_ndft_mfma(const int32_t* __restrict__
                                                      const int32_t* __restrict__ active,
                                                      int32_t n_active, GridDev g, int n_wtiles,
                                                      float* __restrict__ power, WorkDev wk) {
+    static_assert(NB == 1 || NB == 2 || NB == 4, "MFMA tiles per wave");
     __shared__ EvStage st[64];
     const int lane = threadIdx.x;
     const int r32 = lane & 31;
     const bool upper = lane >= 32;
-    // lower lanes form U(row r32) = a exp(i 2 pi (A + 32 r32 D)/Q); upper lanes V(col r32)
-    const uint32_t m = upper ? (uint32_t)r32 : 32u * (uint32_t)r32;
+    const uint32_t mU = 32u * (uint32_t)lane;  // U row `lane` of the tile pair (0, 1)
+    const uint32_t mV = (uint32_t)r32;         // V column
     int64_t iter = 0;
     Unit un;
     while (next_unit<MODE>(wk, row_ptr, active, n_active, n_wtiles, iter, un)) {
@@ -327,32 +339,33 @@ __global__ __launch_bounds__(64, 2) void k_ndft_mfma(const int32_t* __restrict__
             for (int r = 0; r < 16; ++r) { cre[b][r] = 0.0f; cim[b][r] = 0.0f; }
         }
         for (int32_t c0 = un.beg; c0 < un.end; c0 += 64) {
-            stage_event(st, lane, c0, un.end, t_rel, av, f_tile, g, 1024u);
+            stage_event(st, lane, c0, un.end, t_rel, av, f_tile, g, 2048u);
             __syncthreads();
             const int ne = (un.end - c0) < 64 ? (un.end - c0) : 64;
             // software pipelined: the next event's phasors are formed while this
             // event's MFMAs run (no branch inside the body, so they interleave)
-            MfOps o = mf_operands(st[0], upper, m);
+            MfOps o = mf_operands(st[0], upper, mU, mV);
             for (int k = 0; k < ne; ++k) {
                 const EvStage sn = st[k + 1 < ne ? k + 1 : k];
-                float aop = o.aop, uc = o.uc, us = o.us;
-                const float bre = o.bre, bim = o.bim, wc = o.wc, ws = o.ws;
-#pragma unroll
-                for (int b = 0; b < NB; ++b) {
-                    cre[b] = __builtin_amdgcn_mfma_f32_32x32x2f32(aop, bre, cre[b], 0, 0, 0);
-                    cim[b] = __builtin_amdgcn_mfma_f32_32x32x2f32(aop, bim, cim[b], 0, 0, 0);
-                    if (b + 1 < NB) {
-                        // next 32-row tile of U: multiply by the step phasor
-                        const float nr = uc * wc - us * ws;
-                        const float ni = uc * ws + us * wc;
-                        uc = nr;
-                        us = ni;
-                        const auto p = __builtin_amdgcn_permlane32_swap(
-                            __float_as_uint(us), __float_as_uint(us), false, false);
-                        aop = upper ? __uint_as_float(p[0]) : uc;
-                    }
+                cre[0] = __builtin_amdgcn_mfma_f32_32x32x2f32(o.a0, o.bre, cre[0], 0, 0, 0);
+                cim[0] = __builtin_amdgcn_mfma_f32_32x32x2f32(o.a0, o.bim, cim[0], 0, 0, 0);
+                if constexpr (NB >= 2) {
+                    cre[1] = __builtin_amdgcn_mfma_f32_32x32x2f32(o.a1, o.bre, cre[1], 0, 0, 0);
+                    cim[1] = __builtin_amdgcn_mfma_f32_32x32x2f32(o.a1, o.bim, cim[1], 0, 0, 0);
                 }
-                o = mf_operands(sn, upper, m);
+                if constexpr (NB >= 4) {
+                    // tiles 2 and 3: the pair's U rows rotated by 64 rows (2048 bins)
+                    const float uc = o.uc * o.wc - o.us * o.ws;
+                    const float us = o.uc * o.ws + o.us * o.wc;
+                    const auto p = __builtin_amdgcn_permlane32_swap(
+                        __float_as_uint(uc), __float_as_uint(us), false, false);
+                    const float a2 = __uint_as_float(p[0]), a3 = __uint_as_float(p[1]);
+                    cre[2] = __builtin_amdgcn_mfma_f32_32x32x2f32(a2, o.bre, cre[2], 0, 0, 0);
+                    cim[2] = __builtin_amdgcn_mfma_f32_32x32x2f32(a2, o.bim, cim[2], 0, 0, 0);
+                    cre[3] = __builtin_amdgcn_mfma_f32_32x32x2f32(a3, o.bre, cre[3], 0, 0, 0);
+                    cim[3] = __builtin_amdgcn_mfma_f32_32x32x2f32(a3, o.bim, cim[3], 0, 0, 0);
+                }
+                o = mf_operands(sn, upper, mU, mV);
             }
             __syncthreads();
         }
