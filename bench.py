@@ -32,6 +32,7 @@ sys.path.insert(0, ROOT)
 FP32_PEAK_TFLOPS = 157.3       # MI355X FP32 vector and FP32 matrix (dense), published
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, published
 FLOP_PER_EVENT_BIN = 8         # one complex multiply-accumulate per event and bin
+SOFT_FLOP_PER_EVENT_HARMONIC = 16  # forward complex MAC (8) + backward Re/Im of conj(F) z (8)
 
 WORKLOADS = {
     "large_1280x720": "large_window",
@@ -55,6 +56,9 @@ def parse():
                     help="target CPU time of the oracle baseline sample (0 = skip)")
     ap.add_argument("--stream-steps", type=int, default=400, help="timed stream steps (0 = skip)")
     ap.add_argument("--plain-frames", type=int, default=15, help="plain recompute frames timed")
+    ap.add_argument("--soft-windows", type=int, default=16,
+                    help="346x260 labelled windows in the soft-comb training leg (0 = skip)")
+    ap.add_argument("--soft-steps", type=int, default=10, help="timed soft-comb training steps")
     ap.add_argument("--autotune-cache", default=None,
                     help="JSON-lines autotuner cache: read the launch from it, or time the "
                          "candidates and append the winner (default: always time)")
@@ -153,6 +157,81 @@ def load_traffic(kernel_tag, digest):
     return rec.get("bytes_per_launch")
 
 
+def soft_leg(args, D, synth):
+    """Soft comb training step (forward + backward through the library kernels)
+    over a batch of labelled 346x260, 50 ms windows; the FP64 oracle's forward +
+    backward on a sample of one window's pixels beside it."""
+    import torch
+    import oracle
+    from paper_2603_08386_amd import autograd as AG
+    from paper_2603_08386_amd import tune
+
+    wins = [synth.medium_window(400 + i, n_drones=4) for i in range(args.soft_windows)]
+    data = [tune.batch(tune.prepare(wins, device="cuda:0"))]  # one graph: one launch each way
+    nh = data[0].graph.nh
+    ev_h = 0
+    for d in data:
+        rp, act = d.graph.row_ptr, d.graph.active.long()
+        ev_h += int((rp[act + 1] - rp[act]).sum().item()) * nh
+    med, sd = tune._score_scale(data, torch.float32)
+    beta = 4.0 / sd
+    w = torch.full((nh,), 1.0 / nh, device="cuda:0", requires_grad=True)
+    tau = torch.tensor([med], device="cuda:0", requires_grad=True)
+    stream = torch.cuda.current_stream()
+    fwd_ms, bwd_ms, step_ms = [], [], []
+    for it in range(2 + args.soft_steps):
+        e0, e1, e2 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
+        e0.record(stream)
+        loss = tune.bce_loss(data, w, tau, beta)
+        e1.record(stream)
+        loss.backward()
+        e2.record(stream)
+        torch.cuda.synchronize()
+        w.grad = None
+        tau.grad = None
+        if it >= 2:
+            fwd_ms.append(e0.elapsed_time(e1))
+            bwd_ms.append(e1.elapsed_time(e2))
+            step_ms.append(e0.elapsed_time(e2))
+    ms = float(np.median(step_ms))
+    flops = SOFT_FLOP_PER_EVENT_HARMONIC * ev_h
+    tflops = flops / (ms * 1e-3) / 1e12
+    # oracle: FP64 forward + backward on a uniform sample of one window's pixels
+    d0 = data[0]
+    G = d0.graph
+    rp = G.row_ptr.cpu().numpy()
+    t_rel = G.t_rel.cpu().numpy().view(np.uint32)
+    sgn = G.sgn.double().cpu().numpy()
+    act = G.active.cpu().numpy()
+    f0 = G.f0_mhz.cpu().numpy()
+    rng = np.random.default_rng(0)
+    pick = np.sort(rng.choice(act.size, min(act.size, 160000), replace=False))
+    e = np.ones(max(int(rp[-1]), 1))
+    dt = np.zeros_like(e)
+    wv = np.full(nh, 1.0 / nh)
+    t_a = time.perf_counter()
+    s, phat, Fr, Fi = oracle.soft_comb_forward(rp, t_rel, sgn, e, dt, act[pick], f0[pick], nh,
+                                               G.f_max_mhz, wv, med, beta)
+    oracle.soft_comb_backward(rp, t_rel, sgn, e, dt, act[pick], f0[pick], nh, G.f_max_mhz, wv,
+                              beta, s, phat, Fr, Fi, np.ones_like(s))
+    cpu_s = time.perf_counter() - t_a
+    cpu_evh = int(np.sum(rp[act[pick] + 1] - rp[act[pick]])) * nh
+    return {
+        "workload": f"{args.soft_windows} labelled 346x260 windows, 50 ms, {nh} harmonics",
+        "event_harmonics": ev_h, "ms_per_step": ms,
+        "fwd_ms": float(np.median(fwd_ms)), "bwd_ms": float(np.median(bwd_ms)),
+        "event_harmonics_per_s": ev_h / (ms * 1e-3),
+        "roofline": {"bound": "alu", "achieved": tflops, "peak": FP32_PEAK_TFLOPS,
+                     "unit": "TFLOP/s", "frac": tflops / FP32_PEAK_TFLOPS, "traffic": None,
+                     "algorithmic": f"{SOFT_FLOP_PER_EVENT_HARMONIC} FLOP x {ev_h} "
+                                    "event-harmonics per training step"},
+        "cpu_oracle": {"value": cpu_evh / cpu_s, "unit": "event*harmonics/s", "cores": 1,
+                       "kind": "oracle", "sample": f"{pick.size} uniformly sampled pixels of the "
+                                                   f"batch, forward + backward, FP64, "
+                                                   f"{cpu_s:.1f} s"},
+    }
+
+
 def cpu_baseline(win, target_s):
     """Oracle NDFT + flatness + comb on a uniform random sample of active pixels
     (single thread), scaled to pixel-bins per second."""
@@ -171,9 +250,19 @@ def cpu_baseline(win, target_s):
         oracle.score_rows(P, win.grid, win.params)
         spent += time.perf_counter() - t0
         done_pix += rows.size
+    cpu = "unknown CPU"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    cpu = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
     return dict(value=done_pix * K / spent, unit="pixel*bins/s", cores=1, kind="oracle",
                 sample=f"{done_pix} uniformly sampled active pixels of the same window "
-                       f"(NDFT power + flatness + comb, FP64, one thread), {spent:.1f} s")
+                       f"(NDFT power + flatness + comb, FP64, one thread of {os.cpu_count()} "
+                       f"on {cpu}), {spent:.1f} s")
 
 
 def stream_leg(args, D, synth, launch):
@@ -394,6 +483,9 @@ def main():
         out["stream"] = stream_leg(args, D, synth, launch)
         out["frame_latency_ms"]["stream_p50"] = out["stream"]["p50_ms"]
         out["frame_latency_ms"]["stream_p99"] = out["stream"]["p99_ms"]
+    if args.soft_windows > 0:
+        print("[bench] soft comb leg", file=sys.stderr, flush=True)
+        out["soft_comb"] = soft_leg(args, D, synth)
     if args.cpu_seconds > 0:
         print("[bench] cpu baseline", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(win, args.cpu_seconds)

@@ -656,7 +656,7 @@ __global__ __launch_bounds__(kFT) void k_comb_fast(const float* __restrict__ pow
                 const int cm = centre_of(i, m);
                 smax += sP[padk(cm)];
                 const int lo = (cm - dk) > ph + 1 ? (cm - dk) : ph + 1;
-                for (int k = lo; k <= cm + dk; ++k) {
+                auto take = [&](int k) {
                     const uint8_t c = sCode[padk(k)];
                     ++hsize;
                     if (c == kCodeBelow) ++below;
@@ -664,6 +664,25 @@ __global__ __launch_bounds__(kFT) void k_comb_fast(const float* __restrict__ pow
                         if (nin < kInbCap) inr[nin++] = (int)c;
                         else spill = true;
                     }
+                };
+                if (DKT >= 0) {
+                    // fixed window width: the reads are issued together
+                    constexpr int D = DKT >= 0 ? DKT : 0;
+                    uint8_t cw[2 * D + 1];
+#pragma unroll
+                    for (int q = 0; q <= 2 * D; ++q) cw[q] = sCode[padk(cm - D + q)];
+#pragma unroll
+                    for (int q = 0; q <= 2 * D; ++q) {
+                        if (cm - D + q < lo) continue;  // bin already in the previous window
+                        ++hsize;
+                        if (cw[q] == kCodeBelow) ++below;
+                        else if (cw[q] < kCodeCand) {
+                            if (nin < kInbCap) inr[nin++] = (int)cw[q];
+                            else spill = true;
+                        }
+                    }
+                } else {
+                    for (int k = lo; k <= cm + dk; ++k) take(k);
                 }
                 ph = cm + dk;
             }
@@ -710,6 +729,8 @@ __global__ __launch_bounds__(kFT) void k_comb_fast(const float* __restrict__ pow
     if (snr_all == nullptr && den_lo > 0.0f) {
         const float r_hi = 1.0f / den_hi, r_lo = 1.0f / den_lo;
         // N of candidate i (the value the exact evaluation uses), -1 if inadmissible
+        // (centres grow with m, so the valid harmonics are a prefix; the
+        // reciprocal is approximate, which the bounds' margin covers)
         auto n_of = [&](int i) -> float {
             int mv = 0;
             float smax = 0.0f;
@@ -717,12 +738,12 @@ __global__ __launch_bounds__(kFT) void k_comb_fast(const float* __restrict__ pow
             for (int m = 1; m <= (MT > 0 ? MT : 32); ++m) {
                 if (m > M) break;
                 const int cm = centre_of(i, m);
-                const bool val = cm + dk <= K - 1 && mv == m - 1;
+                const bool val = cm + dk <= K - 1;
                 const float wmx = sP[padk(val ? cm : dk)];
                 smax += val ? wmx : 0.0f;
                 mv += val ? 1 : 0;
             }
-            return mv >= ca.h_min ? smax / (float)mv : -1.0f;
+            return mv >= ca.h_min ? smax * __builtin_amdgcn_rcpf((float)mv) : -1.0f;
         };
         float lb = 0.0f;
         for (int i = dk + tid; i <= i_max; i += kFT) lb = fmaxf(lb, n_of(i) * r_hi);

@@ -7,10 +7,13 @@
 //   theta = 2 pi [ ((h f0 t_e) mod 1e9) / 1e9 + h f0 dt_e / 1e9 ]   (f0 in mHz)
 //   P^_h  = |F_h|^2 / n   (h f0 <= f_max, else 0)
 //   s     = sigmoid(beta (sum_h w_h P^_h - tau)).
+// Since theta_h = h theta_1 (mod 2 pi) exactly, each event needs one exact
+// phase reduction and one sin/cos; the harmonics follow by complex
+// multiplication with exp(i theta_1).
 // Forward: one wavefront per pixel, events on lanes, 2 nh accumulators per
 // lane, butterfly reduction in a fixed order.  Backward: per-event gradients
 // in the same layout; the pixel partials of dL/dw_h and dL/dtau are written
-// per pixel and summed by one workgroup in a fixed order (deterministic).
+// per pixel and summed in two fixed-order stages (deterministic).
 // Templated on float and double (the double instantiation serves gradcheck).
 #include "ddhf_internal.h"
 
@@ -40,13 +43,6 @@ __device__ __forceinline__ T phase_rev(int64_t f, uint32_t t, T dt) {
 }
 
 template <typename T>
-__device__ __forceinline__ T wave_sum_t(T v) {
-#pragma unroll
-    for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d, 64);
-    return v;
-}
-
-template <typename T>
 __global__ __launch_bounds__(64) void k_soft_fwd(const int32_t* __restrict__ row_ptr,
                                                  const uint32_t* __restrict__ t_rel,
                                                  const T* __restrict__ sgn, const T* __restrict__ ew,
@@ -66,20 +62,23 @@ __global__ __launch_bounds__(64) void k_soft_fwd(const int32_t* __restrict__ row
     T re[kMaxHarm], im[kMaxHarm];
 #pragma unroll
     for (int h = 0; h < kMaxHarm; ++h) { re[h] = (T)0; im[h] = (T)0; }
+    // harmonics h + 1 with (h + 1) f0 <= f_max form a prefix
+    const int hv = fu > 0 ? (int)(f_max / fu < (int64_t)nh ? f_max / fu : (int64_t)nh) : 0;
     for (int32_t k = b + lane; k < e; k += 64) {
         const uint32_t t = t_rel[k];
         const T a = sgn[k] * ew[k];
         const T d = dt[k];
+        T s1, c1;
+        sincos_rev<T>(phase_rev<T>(fu, t, d), s1, c1);
+        T zc = c1, zs = s1;  // exp(i (h + 1) theta_1)
 #pragma unroll
         for (int h = 0; h < kMaxHarm; ++h) {
-            if (h < nh) {
-                const int64_t f = (int64_t)(h + 1) * fu;
-                if (fu > 0 && f <= f_max) {
-                    T sn, cs;
-                    sincos_rev<T>(phase_rev<T>(f, t, d), sn, cs);
-                    re[h] += a * cs;
-                    im[h] += a * sn;
-                }
+            if (h < hv) {
+                re[h] += a * zc;
+                im[h] += a * zs;
+                const T nc = zc * c1 - zs * s1;
+                zs = zc * s1 + zs * c1;
+                zc = nc;
             }
         }
     }
@@ -88,8 +87,8 @@ __global__ __launch_bounds__(64) void k_soft_fwd(const int32_t* __restrict__ row
 #pragma unroll
     for (int h = 0; h < kMaxHarm; ++h) {
         if (h < nh) {
-            const T R = wave_sum_t(re[h]);
-            const T I = wave_sum_t(im[h]);
+            const T R = wave_sum(re[h]);  // fixed-order DPP reduction
+            const T I = wave_sum(im[h]);
             const T ph = n > (T)0 ? (R * R + I * I) / n : (T)0;
             x += w[h] * ph;
             if (lane == 0) {
@@ -129,27 +128,30 @@ __global__ __launch_bounds__(64) void k_soft_bwd(const int32_t* __restrict__ row
         else v = -gx;
         part[(int64_t)u * (nh + 1) + lane] = v;
     }
+    const int hv = fu > 0 ? (int)(f_max / fu < (int64_t)nh ? f_max / fu : (int64_t)nh) : 0;
+    const T tw = (T)(2.0 * M_PI * (double)fu * 1e-9);  // d theta_1 / d dt (per us)
     for (int32_t k = b + lane; k < e; k += 64) {
         const uint32_t t = t_rel[k];
         const T p = sgn[k];
         const T ek = ew[k];
         const T d = dt[k];
+        T s1, c1;
+        sincos_rev<T>(phase_rev<T>(fu, t, d), s1, c1);
+        T zc = c1, zs = s1;
         T ge = (T)0, gd = (T)0;
 #pragma unroll
         for (int h = 0; h < kMaxHarm; ++h) {
-            if (h < nh) {
-                const int64_t f = (int64_t)(h + 1) * fu;
-                if (fu > 0 && f <= f_max) {
-                    T sn, cs;
-                    sincos_rev<T>(phase_rev<T>(f, t, d), sn, cs);
-                    const T Fr = F[((int64_t)u * nh + h) * 2];
-                    const T Fi = F[((int64_t)u * nh + h) * 2 + 1];
-                    const T gP = gx * w[h] / n;
-                    const T rp = Fr * cs + Fi * sn;   // Re(conj(F) e^{i theta})
-                    const T ip = Fr * sn - Fi * cs;   // Im(conj(F) e^{i theta})
-                    ge += gP * (T)2 * p * rp;
-                    gd += gP * ((T)-2 * p * ek * ip) * (T)(2.0 * M_PI * (double)f * 1e-9);
-                }
+            if (h < hv) {
+                const T Fr = F[((int64_t)u * nh + h) * 2];
+                const T Fi = F[((int64_t)u * nh + h) * 2 + 1];
+                const T gP = gx * w[h] / n;
+                const T rp = Fr * zc + Fi * zs;   // Re(conj(F) e^{i theta})
+                const T ip = Fr * zs - Fi * zc;   // Im(conj(F) e^{i theta})
+                ge += gP * (T)2 * p * rp;
+                gd += gP * ((T)-2 * p * ek * ip) * (tw * (T)(h + 1));
+                const T nc = zc * c1 - zs * s1;
+                zs = zc * s1 + zs * c1;
+                zc = nc;
             }
         }
         g_e[k] = ge;
@@ -157,16 +159,39 @@ __global__ __launch_bounds__(64) void k_soft_bwd(const int32_t* __restrict__ row
     }
 }
 
-// Sums part[u][j] over u for each j in a fixed order (one workgroup).
+// Sums part[u][j] over u for each j in a fixed order: stage 1, each of
+// kSoftRedBlocks workgroups sums a contiguous slice of pixels; stage 2, one
+// workgroup sums the slices (both with fixed trees, so bit-reproducible).
+constexpr int kSoftRedBlocks = 256;
+
 template <typename T>
-__global__ __launch_bounds__(256) void k_soft_reduce(const T* __restrict__ part, int32_t n_active,
-                                                     int32_t nh, T* __restrict__ g_w,
-                                                     T* __restrict__ g_tau) {
+__global__ __launch_bounds__(256) void k_soft_reduce1(const T* __restrict__ part, int32_t n_active,
+                                                      int32_t nh, T* __restrict__ slices) {
     __shared__ T red[256];
+    const int32_t per = (n_active + kSoftRedBlocks - 1) / kSoftRedBlocks;
+    const int32_t u0 = blockIdx.x * per;
+    const int32_t u1 = u0 + per < n_active ? u0 + per : n_active;
     for (int j = 0; j <= nh; ++j) {
         T acc = (T)0;
-        for (int32_t u = threadIdx.x; u < n_active; u += 256) acc += part[(int64_t)u * (nh + 1) + j];
+        for (int32_t u = u0 + threadIdx.x; u < u1; u += 256) acc += part[(int64_t)u * (nh + 1) + j];
         red[threadIdx.x] = acc;
+        __syncthreads();
+        for (int st = 128; st >= 1; st >>= 1) {
+            if (threadIdx.x < st) red[threadIdx.x] += red[threadIdx.x + st];
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) slices[(int64_t)blockIdx.x * (nh + 1) + j] = red[0];
+        __syncthreads();
+    }
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_soft_reduce2(const T* __restrict__ slices, int32_t nh,
+                                                      T* __restrict__ g_w, T* __restrict__ g_tau) {
+    __shared__ T red[256];
+    for (int j = 0; j <= nh; ++j) {
+        red[threadIdx.x] = threadIdx.x < kSoftRedBlocks ? slices[(int64_t)threadIdx.x * (nh + 1) + j]
+                                                        : (T)0;
         __syncthreads();
         for (int st = 128; st >= 1; st >>= 1) {
             if (threadIdx.x < st) red[threadIdx.x] += red[threadIdx.x + st];
@@ -219,7 +244,9 @@ extern "C" int ddhf_soft_comb_backward_workspace_size(int32_t n_active, int32_t 
                                                       size_t* bytes) {
     if (!bytes || n_active < 0 || nh < 1 || nh > kMaxHarm || (dtype != 0 && dtype != 1))
         return DDHF_EINVAL;
-    *bytes = align_up((size_t)(n_active > 0 ? n_active : 1) * (nh + 1) * (dtype ? 8 : 4));
+    const size_t es = dtype ? 8 : 4;
+    *bytes = align_up((size_t)(n_active > 0 ? n_active : 1) * (nh + 1) * es) +
+             align_up((size_t)kSoftRedBlocks * (nh + 1) * es);
     return DDHF_OK;
 }
 
@@ -255,12 +282,19 @@ extern "C" int ddhf_soft_comb_backward(const int32_t* row_ptr, const uint32_t* t
                                (const double*)g_s, (double*)g_e, (double*)g_dt, (double*)ws);
         DDHF_LAUNCH_CHECK();
     }
-    if (dtype == 0)
-        hipLaunchKernelGGL(k_soft_reduce<float>, dim3(1), dim3(256), 0, st, (const float*)ws,
-                           n_active, nh, (float*)g_w, (float*)g_tau);
-    else
-        hipLaunchKernelGGL(k_soft_reduce<double>, dim3(1), dim3(256), 0, st, (const double*)ws,
-                           n_active, nh, (double*)g_w, (double*)g_tau);
+    const size_t es = dtype ? 8 : 4;
+    char* slices = (char*)ws + align_up((size_t)(n_active > 0 ? n_active : 1) * (nh + 1) * es);
+    if (dtype == 0) {
+        hipLaunchKernelGGL(k_soft_reduce1<float>, dim3(kSoftRedBlocks), dim3(256), 0, st,
+                           (const float*)ws, n_active, nh, (float*)slices);
+        hipLaunchKernelGGL(k_soft_reduce2<float>, dim3(1), dim3(256), 0, st,
+                           (const float*)slices, nh, (float*)g_w, (float*)g_tau);
+    } else {
+        hipLaunchKernelGGL(k_soft_reduce1<double>, dim3(kSoftRedBlocks), dim3(256), 0, st,
+                           (const double*)ws, n_active, nh, (double*)slices);
+        hipLaunchKernelGGL(k_soft_reduce2<double>, dim3(1), dim3(256), 0, st,
+                           (const double*)slices, nh, (double*)g_w, (double*)g_tau);
+    }
     DDHF_LAUNCH_CHECK();
     return DDHF_OK;
 }

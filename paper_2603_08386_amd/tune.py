@@ -42,6 +42,33 @@ def prepare(windows: List[synth.Window], device="cuda", nh: int = 8, beta: float
     return out
 
 
+def batch(data: List[Labelled]) -> Labelled:
+    """Concatenates labelled windows into one graph (pixel and event indices
+    offset per window), so a loss over all of them is one forward and one
+    backward launch."""
+    gs = [d.graph for d in data]
+    dev = gs[0].row_ptr.device
+    rps, acts = [], []
+    ev_off, px_off = 0, 0
+    for d in data:
+        rp = d.graph.row_ptr.to(torch.int64)
+        n_ev = int(rp[-1].item())
+        rps.append(rp[:-1] + ev_off)
+        acts.append(d.graph.active.to(torch.int64) + px_off)
+        ev_off += n_ev
+        px_off += rp.numel() - 1
+    rps.append(torch.tensor([ev_off], dtype=torch.int64, device=dev))
+    assert ev_off < 2**31 and px_off < 2**31
+    cut = lambda x, d: x[:int(d.graph.row_ptr[-1].item())]
+    G = AG.SoftCombGraph(
+        torch.cat(rps).to(torch.int32), torch.cat([cut(d.graph.t_rel, d) for d in data]),
+        torch.cat([cut(d.graph.sgn, d) for d in data]), torch.cat(acts).to(torch.int32),
+        torch.cat([g.f0_mhz for g in gs]), gs[0].nh, gs[0].f_max_mhz, gs[0].beta)
+    return Labelled(G, torch.cat([d.label for d in data]),
+                    torch.cat([cut(d.e, d) for d in data]),
+                    torch.cat([cut(d.dt, d) for d in data]))
+
+
 def _score_scale(data: List[Labelled], dtype):
     """Median and spread of the uniform-weight comb sum x = sum_h P^_h / nh over
     all active pixels; they start tau and set beta."""

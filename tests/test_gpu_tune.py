@@ -27,3 +27,20 @@ def test_gradient_tuning_beats_or_matches_grid_search():
     assert g["accuracy"] >= r["accuracy"] - 0.005
     assert g["accuracy"] >= 0.9
     assert np.all(np.isfinite(g["w"].cpu().numpy()))
+
+
+def test_batched_graph_matches_per_window():
+    wins = [synth.medium_window(410 + i, n_drones=4) for i in range(3)]
+    banner("tune: batch")
+    data = tune.prepare(wins, device=DEV)
+    b = tune.batch(data)
+    nh = data[0].graph.nh
+    w = torch.linspace(0.05, 0.2, nh, device=DEV, requires_grad=True)
+    tau = torch.tensor([3.0], device=DEV, requires_grad=True)
+    l1 = tune.bce_loss(data, w, tau, 0.5)
+    g1 = torch.autograd.grad(l1, (w, tau))
+    l2 = tune.bce_loss([b], w, tau, 0.5)
+    g2 = torch.autograd.grad(l2, (w, tau))
+    assert abs(l1.item() - l2.item()) <= 1e-5 * max(1.0, abs(l1.item()))
+    for x, y in zip(g1, g2):
+        assert torch.allclose(x, y, rtol=1e-4, atol=1e-7)
