@@ -101,12 +101,15 @@ def _pmc_mean_kib(path, counter, name_part):
     return sum(vals) / len(vals), len(vals)
 
 
-TRAFFIC_KERNELS = {
-    # tag prefix: (kernel-name fragment, sources whose digest keys the record)
-    "ndft_mfma": ("k_ndft_mfma", ["ndft.hip", "ddhf_internal.h"]),
-    "ndft_valu": ("k_ndft_valu", ["ndft.hip", "ddhf_internal.h"]),
-    "comb_fast": ("k_comb_fast", ["comb.hip", "ddhf_internal.h"]),
-}
+# sources whose digest keys a traffic record
+TRAFFIC_SOURCES = {"ndft": ["ndft.hip", "ddhf_internal.h"], "comb": ["comb.hip", "ddhf_internal.h"]}
+
+
+def ndft_tag(kernel, bpl):
+    """Record tag and rocprofv3 kernel-name fragment of one NDFT instantiation."""
+    if kernel == "mfma":
+        return f"ndft_mfma{bpl}", f"k_ndft_mfma<{bpl // 16}, 0>"
+    return f"ndft_valu{bpl}", f"k_ndft_valu<{bpl}, 0>"
 
 
 def traffic_summary(args, fetch_csv, write_csv, cal_fetch_csv, cal_write_csv):
@@ -119,8 +122,9 @@ def traffic_summary(args, fetch_csv, write_csv, cal_fetch_csv, cal_write_csv):
     cw, _ = _pmc_mean_kib(cal_write_csv, "WRITE_SIZE", "copyBuffer")
     fetch_scale = COPY_BYTES / (cf * 1024.0)
     write_scale = COPY_BYTES / (cw * 1024.0)
-    for prefix in (f"ndft_{args.kernel}", "comb_fast"):
-        name, srcs = TRAFFIC_KERNELS[prefix]
+    ntag, nname = ndft_tag(args.kernel, args.bpl)
+    for prefix, name, srcs in ((ntag, nname, TRAFFIC_SOURCES["ndft"]),
+                               ("comb_fast", "k_comb_fast<", TRAFFIC_SOURCES["comb"])):
         f, nf = _pmc_mean_kib(fetch_csv, "FETCH_SIZE", name)
         w, nw = _pmc_mean_kib(write_csv, "WRITE_SIZE", name)
         rec = {"kernel": name, "workload": args.workload,
@@ -430,11 +434,12 @@ def main():
     ndft_ms = float(np.mean(stage_ms["ndft"]))
     flops = FLOP_PER_EVENT_BIN * ev_bins
     achieved_tflops = flops / (ndft_ms * 1e-3) / 1e12
-    tag = "ndft_valu" if launch.kernel == D.DDHF_KERNEL_VALU else "ndft_mfma"
-    traffic = load_traffic(f"{tag}_{args.workload}",
-                           kernel_source_digest(TRAFFIC_KERNELS[tag][1]))
-    roof_ndft = {"bound": "alu" if launch.kernel == D.DDHF_KERNEL_VALU else "mfma",
-                 "kernel": TRAFFIC_KERNELS[tag][0], "achieved": achieved_tflops,
+    kname = "valu" if launch.kernel == D.DDHF_KERNEL_VALU else "mfma"
+    tag, kfrag = ndft_tag(kname, launch.bins_per_lane)
+    traffic = (load_traffic(f"{tag}_{args.workload}", kernel_source_digest(TRAFFIC_SOURCES["ndft"]))
+               if launch.split_events == 0 and launch.persistent == 0 else None)
+    roof_ndft = {"bound": "alu" if kname == "valu" else "mfma",
+                 "kernel": kfrag, "achieved": achieved_tflops,
                  "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
                  "frac": achieved_tflops / FP32_PEAK_TFLOPS, "traffic": traffic,
                  "ms": ndft_ms, "algorithmic": f"{FLOP_PER_EVENT_BIN} FLOP x {ev_bins} event-bins"}
@@ -444,7 +449,7 @@ def main():
     roof_comb = {"bound": "hbm", "kernel": "k_comb_fast", "achieved": comb_gbs,
                  "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": comb_gbs / HBM_PEAK_GBS,
                  "traffic": load_traffic(f"comb_fast_{args.workload}",
-                                         kernel_source_digest(TRAFFIC_KERNELS["comb_fast"][1])),
+                                         kernel_source_digest(TRAFFIC_SOURCES["comb"])),
                  "ms": comb_ms, "algorithmic": f"{comb_bytes} bytes (P read + per-pixel outputs)"}
     dominant = roof_ndft if ndft_ms >= comb_ms else roof_comb
 
