@@ -2,12 +2,16 @@
 // (Sec. 3.5 "Segmentation Mask Processing", Eq. 12).
 //
 // mask: n_p >= n_min, SF <= tau_sf (Eq. 7 gate), SNR >= tau_comb (Eq. 11).
-// Components: union-find over the mask with atomicMin linking (a root is
-// always linked under a smaller index), so after compression every label is
-// the smallest pixel index of its component -- a deterministic labelling.
-// Boxes: per-root integer atomics; the representative pixel is the member with
-// the highest score (lowest index on ties), packed as (score bits, ~index) in
-// one 64-bit max.  Merge: a single workgroup loads the boxes that pass the
+// Components: union-find with atomicMin linking (a root is always linked
+// under a smaller index), so after compression every label is the smallest
+// pixel index of its component -- a deterministic labelling.  Each 32x16 tile
+// is first labelled by one workgroup in LDS; only pixels on tile borders then
+// link across tiles in global memory.
+// Boxes: per-root integer min / max / sum; the representative pixel is the
+// member with the highest score (lowest index on ties), packed as (score
+// bits, ~index) in one 64-bit max.  Each tile reduces its pixels per root in
+// LDS (wavefronts whose pixels share a root first reduce in registers) and
+// issues one global atomic per field and root.  Merge: a single workgroup loads the boxes that pass the
 // area filter, orders them by root pixel, and repeats rounds of "union every
 // pair closer than alpha times the largest side, then replace each group by
 // its union box" until a round merges nothing.
@@ -102,20 +106,82 @@ __global__ void k_det_mask(const int32_t* __restrict__ active, const int32_t* __
     }
 }
 
-// The kernels below walk the pixels in raster order (whatever the order of the
-// active list), so a wavefront covers neighbouring pixels.
-__global__ void k_det_union(int32_t npix, int32_t W, const uint8_t* __restrict__ mask,
-                            int32_t* labels) {
+// ---- tile labelling -------------------------------------------------------
+constexpr int kTW = 32, kTH = 16, kTP = kTW * kTH;  // one workgroup per tile
+constexpr int kSlots = 64;                           // distinct roots kept per tile
+
+__device__ __forceinline__ int32_t lds_find(int32_t* lab, int32_t p) {
+    int32_t q = lab[p];
+    while (q != p) {
+        p = q;
+        q = lab[p];
+    }
+    return p;
+}
+
+__device__ __forceinline__ void lds_union(int32_t* lab, int32_t a, int32_t b) {
+    for (;;) {
+        a = lds_find(lab, a);
+        b = lds_find(lab, b);
+        if (a == b) return;
+        if (a < b) { int32_t t = a; a = b; b = t; }
+        const int32_t old = atomicMin(&lab[a], b);
+        if (old == a) return;
+        a = old;
+    }
+}
+
+// Labels the components of one tile in LDS (tile-local indices are row-major,
+// so the smallest local index is the smallest global index) and points every
+// mask pixel at its tile-local root.
+__global__ __launch_bounds__(256) void k_det_tile(int32_t W, int32_t H,
+                                                  const uint8_t* __restrict__ mask,
+                                                  int32_t* __restrict__ labels) {
+    __shared__ int32_t L[kTP];
+    __shared__ uint8_t M[kTP];
+    const int tx0 = blockIdx.x * kTW, ty0 = blockIdx.y * kTH;
+    for (int i = threadIdx.x; i < kTP; i += blockDim.x) {
+        const int x = tx0 + i % kTW, y = ty0 + i / kTW;
+        const uint8_t m = (x < W && y < H) ? mask[(int64_t)y * W + x] : 0;
+        M[i] = m;
+        L[i] = m ? i : -1;
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < kTP; i += blockDim.x) {
+        if (!M[i]) continue;
+        const int lx = i % kTW, ly = i / kTW;
+        if (lx > 0 && M[i - 1]) lds_union(L, i, i - 1);
+        if (ly > 0) {
+            const int r = i - kTW;
+            if (lx > 0 && M[r - 1]) lds_union(L, i, r - 1);
+            if (M[r]) lds_union(L, i, r);
+            if (lx + 1 < kTW && M[r + 1]) lds_union(L, i, r + 1);
+        }
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < kTP; i += blockDim.x) {
+        if (!M[i]) continue;
+        const int root = lds_find(L, i);
+        const int x = tx0 + i % kTW, y = ty0 + i / kTW;
+        labels[(int64_t)y * W + x] = (ty0 + root / kTW) * W + (tx0 + root % kTW);
+    }
+}
+
+// Links across tile borders: each mask pixel unions with those of its W, NW,
+// N, NE neighbours that lie in another tile (the rest were linked in LDS).
+__global__ void k_det_border(int32_t npix, int32_t W, const uint8_t* __restrict__ mask,
+                             int32_t* labels) {
     const int32_t q = blockIdx.x * blockDim.x + threadIdx.x;
-    if (q >= npix || !mask[q]) return;
+    if (q >= npix) return;
     const int32_t x = q % W, y = q / W;
-    // half neighbourhood: W, NW, N, NE
-    if (x > 0 && mask[q - 1]) uf_union(labels, q, q - 1);
+    const bool left = x % kTW == 0, right = x % kTW == kTW - 1, top = y % kTH == 0;
+    if (!(left || right || top) || !mask[q]) return;
+    if (left && x > 0 && mask[q - 1]) uf_union(labels, q, q - 1);
     if (y > 0) {
         const int32_t r = q - W;
-        if (x > 0 && mask[r - 1]) uf_union(labels, q, r - 1);
-        if (mask[r]) uf_union(labels, q, r);
-        if (x + 1 < W && mask[r + 1]) uf_union(labels, q, r + 1);
+        if ((left || top) && x > 0 && mask[r - 1]) uf_union(labels, q, r - 1);
+        if (top && mask[r]) uf_union(labels, q, r);
+        if ((right || top) && x + 1 < W && mask[r + 1]) uf_union(labels, q, r + 1);
     }
 }
 
@@ -126,57 +192,94 @@ __global__ void k_det_compress(int32_t npix, const uint8_t* __restrict__ mask, i
     __hip_atomic_store(&labels[q], r, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// Box accumulation.  Large components make many lanes share one root, so a
-// wavefront whose mask lanes all share the first lane's root reduces in
-// registers and issues one atomic per field; other waves use per-lane atomics.
-__global__ __launch_bounds__(256) void k_det_accum(int32_t npix, int32_t W,
+// Box accumulation per tile: a slot table of up to kSlots roots in LDS.  A
+// wavefront whose mask lanes share one root reduces in registers first; a
+// root that finds the table full goes straight to global atomics.
+__global__ __launch_bounds__(256) void k_det_accum(int32_t W, int32_t H,
                                                    const uint8_t* __restrict__ mask,
                                                    const int32_t* __restrict__ labels,
                                                    DetectWs d) {
-    const int32_t q = blockIdx.x * blockDim.x + threadIdx.x;
-    int32_t r = -1;
-    if (q < npix && mask[q]) r = labels[q];
-    const bool on = r >= 0;
-    const uint64_t pend = __ballot(on);
-    if (pend == 0) return;
-    const int leader = __ffsll((long long)pend) - 1;
-    const int32_t r0 = __shfl(r, leader, 64);
-    const uint64_t same = __ballot(on && r == r0);
-    const int32_t x = on ? q % W : 0x7FFFFFFF, y = on ? q / W : 0x7FFFFFFF;
-    const unsigned long long key =
-        on ? (((unsigned long long)__float_as_uint(d.psnr[q]) << 32) |
-              (unsigned long long)(0xFFFFFFFFu - (uint32_t)q))
-           : 0ull;
-    if (same == pend) {
-        int32_t x0 = x, y0 = y, x1 = on ? x : -1, y1 = on ? y : -1, c = on ? 1 : 0;
-        unsigned long long k = key;
-#pragma unroll
-        for (int dd = 32; dd >= 1; dd >>= 1) {
-            x0 = min(x0, __shfl_xor(x0, dd, 64));
-            y0 = min(y0, __shfl_xor(y0, dd, 64));
-            x1 = max(x1, __shfl_xor(x1, dd, 64));
-            y1 = max(y1, __shfl_xor(y1, dd, 64));
-            c += __shfl_xor(c, dd, 64);
-            const unsigned long long o = __shfl_xor(k, dd, 64);
-            k = o > k ? o : k;
-        }
-        if (__lane_id() == leader) {
-            atomicMin(&d.x0[r0], x0);
-            atomicMin(&d.y0[r0], y0);
-            atomicMax(&d.x1[r0], x1);
-            atomicMax(&d.y1[r0], y1);
-            atomicAdd(&d.npx[r0], c);
-            atomicMax(&d.rep[r0], k);
-        }
-        return;
+    __shared__ int32_t key[kSlots], sx0[kSlots], sy0[kSlots], sx1[kSlots], sy1[kSlots], sn[kSlots];
+    __shared__ unsigned long long srep[kSlots];
+    const int tid = threadIdx.x;
+    if (tid < kSlots) {
+        key[tid] = -1;
+        sx0[tid] = 0x7FFFFFFF;
+        sy0[tid] = 0x7FFFFFFF;
+        sx1[tid] = -1;
+        sy1[tid] = -1;
+        sn[tid] = 0;
+        srep[tid] = 0ull;
     }
-    if (!on) return;
-    atomicMin(&d.x0[r], x);
-    atomicMin(&d.y0[r], y);
-    atomicMax(&d.x1[r], x);
-    atomicMax(&d.y1[r], y);
-    atomicAdd(&d.npx[r], 1);
-    atomicMax(&d.rep[r], key);
+    __syncthreads();
+    const int tx0 = blockIdx.x * kTW, ty0 = blockIdx.y * kTH;
+    auto add = [&](int32_t r, int32_t x0, int32_t y0, int32_t x1, int32_t y1, int32_t c,
+                   unsigned long long k) {
+        int h = (int)((uint32_t)r * 2654435761u >> 26);  // 6-bit hash
+        for (int probe = 0; probe < kSlots; ++probe) {
+            const int32_t old = atomicCAS(&key[h], -1, r);
+            if (old == -1 || old == r) {
+                atomicMin(&sx0[h], x0);
+                atomicMin(&sy0[h], y0);
+                atomicMax(&sx1[h], x1);
+                atomicMax(&sy1[h], y1);
+                atomicAdd(&sn[h], c);
+                atomicMax(&srep[h], k);
+                return;
+            }
+            h = (h + 1) & (kSlots - 1);
+        }
+        atomicMin(&d.x0[r], x0);
+        atomicMin(&d.y0[r], y0);
+        atomicMax(&d.x1[r], x1);
+        atomicMax(&d.y1[r], y1);
+        atomicAdd(&d.npx[r], c);
+        atomicMax(&d.rep[r], k);
+    };
+    for (int i = tid; i < kTP; i += blockDim.x) {
+        const int x = tx0 + i % kTW, y = ty0 + i / kTW;
+        const int32_t q = y * W + x;
+        int32_t r = -1;
+        if (x < W && y < H && mask[q]) r = labels[q];
+        const bool on = r >= 0;
+        const uint64_t pend = __ballot(on);
+        if (pend == 0) continue;
+        const int leader = __ffsll((long long)pend) - 1;
+        const int32_t r0 = __shfl(r, leader, 64);
+        const uint64_t same = __ballot(on && r == r0);
+        const unsigned long long k =
+            on ? (((unsigned long long)__float_as_uint(d.psnr[q]) << 32) |
+                  (unsigned long long)(0xFFFFFFFFu - (uint32_t)q))
+               : 0ull;
+        if (same == pend) {
+            int32_t x0 = on ? x : 0x7FFFFFFF, y0 = on ? y : 0x7FFFFFFF;
+            int32_t x1 = on ? x : -1, y1 = on ? y : -1, c = on ? 1 : 0;
+            unsigned long long kk = k;
+#pragma unroll
+            for (int dd = 32; dd >= 1; dd >>= 1) {
+                x0 = min(x0, __shfl_xor(x0, dd, 64));
+                y0 = min(y0, __shfl_xor(y0, dd, 64));
+                x1 = max(x1, __shfl_xor(x1, dd, 64));
+                y1 = max(y1, __shfl_xor(y1, dd, 64));
+                c += __shfl_xor(c, dd, 64);
+                const unsigned long long o = __shfl_xor(kk, dd, 64);
+                kk = o > kk ? o : kk;
+            }
+            if (__lane_id() == leader) add(r0, x0, y0, x1, y1, c, kk);
+        } else if (on) {
+            add(r, x, y, x, y, 1, k);
+        }
+    }
+    __syncthreads();
+    if (tid < kSlots && key[tid] >= 0) {
+        const int32_t r = key[tid];
+        atomicMin(&d.x0[r], sx0[tid]);
+        atomicMin(&d.y0[r], sy0[tid]);
+        atomicMax(&d.x1[r], sx1[tid]);
+        atomicMax(&d.y1[r], sy1[tid]);
+        atomicAdd(&d.npx[r], sn[tid]);
+        atomicMax(&d.rep[r], srep[tid]);
+    }
 }
 
 __global__ void k_det_collect(int32_t npix, const uint8_t* __restrict__ mask,
@@ -236,27 +339,6 @@ __device__ __forceinline__ bool close_pair(const MergeLds& L, int i, int j, doub
     const double lhs = (double)(dx2 * dx2 + dy2 * dy2);
     const double tt = 2.0 * alpha * (double)s;
     return lhs < tt * tt;
-}
-
-__device__ int32_t lds_find(int32_t* lab, int32_t p) {
-    int32_t q = lab[p];
-    while (q != p) {
-        p = q;
-        q = lab[p];
-    }
-    return p;
-}
-
-__device__ void lds_union(int32_t* lab, int32_t a, int32_t b) {
-    for (;;) {
-        a = lds_find(lab, a);
-        b = lds_find(lab, b);
-        if (a == b) return;
-        if (a < b) { int32_t t = a; a = b; b = t; }
-        const int32_t old = atomicMin(&lab[a], b);
-        if (old == a) return;
-        a = old;
-    }
 }
 
 // Block bitonic sort of a permutation of the first n slots (padded to a power
@@ -479,11 +561,14 @@ int detect_run(const int32_t* active, const int32_t* row_ptr, const float* sf,
                            n_active, ma, mask, labels, d, n_dev);
         DDHF_LAUNCH_CHECK();
         const dim3 gp(blocks_for(npix, 256));
-        hipLaunchKernelGGL(k_det_union, gp, dim3(256), 0, s, (int32_t)npix, W, mask, labels);
+        const dim3 gt((W + kTW - 1) / kTW, (H + kTH - 1) / kTH);
+        hipLaunchKernelGGL(k_det_tile, gt, dim3(256), 0, s, W, H, mask, labels);
+        DDHF_LAUNCH_CHECK();
+        hipLaunchKernelGGL(k_det_border, gp, dim3(256), 0, s, (int32_t)npix, W, mask, labels);
         DDHF_LAUNCH_CHECK();
         hipLaunchKernelGGL(k_det_compress, gp, dim3(256), 0, s, (int32_t)npix, mask, labels);
         DDHF_LAUNCH_CHECK();
-        hipLaunchKernelGGL(k_det_accum, gp, dim3(256), 0, s, (int32_t)npix, W, mask, labels, d);
+        hipLaunchKernelGGL(k_det_accum, gt, dim3(256), 0, s, W, H, mask, labels, d);
         DDHF_LAUNCH_CHECK();
         hipLaunchKernelGGL(k_det_collect, gp, dim3(256), 0, s, (int32_t)npix, mask, labels,
                            prm->a_min, d);
