@@ -436,7 +436,7 @@ __global__ __launch_bounds__(kFT) void k_comb_fast(const float* __restrict__ pow
     __shared__ Loc l1lo, l1hi, l2lo, l2hi;
     __shared__ uint32_t s_nlist, s_qn;
     __shared__ float s_best[kFT / kWave];
-    __shared__ int s_bi[kFT / kWave];
+    __shared__ uint64_t s_key[kFT / kWave];
 
     const int K = ca.K;
     const int M = MT > 0 ? MT : ca.M;
@@ -745,24 +745,34 @@ __global__ __launch_bounds__(kFT) void k_comb_fast(const float* __restrict__ pow
             }
             return mv >= ca.h_min ? smax * __builtin_amdgcn_rcpf((float)mv) : -1.0f;
         };
+        // the first kKeep rounds keep N in registers for the filter pass
+        constexpr int kKeep = 8;
+        float nv[kKeep];
         float lb = 0.0f;
-        for (int i = dk + tid; i <= i_max; i += kFT) lb = fmaxf(lb, n_of(i) * r_hi);
 #pragma unroll
-        for (int d = 32; d >= 1; d >>= 1) lb = fmaxf(lb, __shfl_xor(lb, d, 64));
+        for (int r = 0; r < kKeep; ++r) {
+            const int i = dk + tid + r * kFT;
+            nv[r] = i <= i_max ? n_of(i) : -1.0f;
+            lb = fmaxf(lb, nv[r] * r_hi);
+        }
+        for (int i = dk + tid + kKeep * kFT; i <= i_max; i += kFT) lb = fmaxf(lb, n_of(i) * r_hi);
+        lb = wave_max(lb);
         if (__lane_id() == 0) s_best[tid / kWave] = lb;
         __syncthreads();
         float thr = 0.0f;
 #pragma unroll
         for (int q = 0; q < kFT / kWave; ++q) thr = fmaxf(thr, s_best[q]);
         thr *= 0.999f;  // margin over the rounding of both bounds
-        for (int i = dk + tid; i <= i_max; i += kFT) {
-            const float n = n_of(i);
+        auto offer = [&](int i, float n) {
             if (n >= 0.0f && n * r_lo >= thr) {
                 const uint32_t pos = atomicAdd(&s_qn, 1u);
                 if (pos < kListCap) sList[pos] = (uint16_t)i;
                 else eval_exact(i);
             }
-        }
+        };
+#pragma unroll
+        for (int r = 0; r < kKeep; ++r) offer(dk + tid + r * kFT, nv[r]);
+        for (int i = dk + tid + kKeep * kFT; i <= i_max; i += kFT) offer(i, n_of(i));
         __syncthreads();
         const int nq = (int)(s_qn < (uint32_t)kListCap ? s_qn : (uint32_t)kListCap);
         for (int e = tid; e < nq; e += kFT) eval_exact((int)sList[e]);
@@ -774,28 +784,19 @@ __global__ __launch_bounds__(kFT) void k_comb_fast(const float* __restrict__ pow
         for (int i = tid; i < K; i += kFT)
             if (i < dk || i > i_max) snr_all[(int64_t)u * K + i] = 0.0f;
     }
-#pragma unroll
-    for (int d = 32; d >= 1; d >>= 1) {
-        const float ob = __shfl_xor(best, d, 64);
-        const int oi = __shfl_xor(best_i, d, 64);
-        const bool take = oi >= 0 && (best_i < 0 || ob > best || (ob == best && oi < best_i));
-        if (take) { best = ob; best_i = oi; }
-    }
-    const int w = tid / kWave;
-    if (__lane_id() == 0) { s_best[w] = best; s_bi[w] = best_i; }
+    // argmax over the workgroup: highest score, lowest bin on ties, as the max
+    // of (score bits << 32 | ~bin); scores are >= 0, so their bits order them
+    uint64_t bk = best_i < 0 ? 0ull
+                             : (((uint64_t)__float_as_uint(best) << 32) |
+                                (uint64_t)(0xFFFFFFFFu - (uint32_t)best_i));
+    bk = wave_max(bk);
+    if (__lane_id() == 0) s_key[tid / kWave] = bk;
     __syncthreads();
     if (tid == 0) {
-        float b = 0.0f;
-        int bi = -1;
-        for (int q = 0; q < kFT / kWave; ++q) {
-            const int oi = s_bi[q];
-            if (oi >= 0 && (bi < 0 || s_best[q] > b || (s_best[q] == b && oi < bi))) {
-                b = s_best[q];
-                bi = oi;
-            }
-        }
-        snr_out[u] = bi < 0 ? 0.0f : b;
-        bin_out[u] = bi;
+        uint64_t b = 0ull;
+        for (int q = 0; q < kFT / kWave; ++q) b = s_key[q] > b ? s_key[q] : b;
+        snr_out[u] = b == 0ull ? 0.0f : __uint_as_float((uint32_t)(b >> 32));
+        bin_out[u] = b == 0ull ? -1 : (int32_t)(0xFFFFFFFFu - (uint32_t)(b & 0xFFFFFFFFull));
     }
 }
 

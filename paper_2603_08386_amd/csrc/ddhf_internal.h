@@ -76,21 +76,24 @@ __device__ __forceinline__ float dpp_f32(float v) {
         __builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, ROWMASK, 0xF, true));
 }
 
-// Inclusive prefix sum across the 64 lanes of a wave (Hillis-Steele inside
-// each row of 16 lanes, then row totals carried by row_bcast:15 / :31).
+// Inclusive scan across the 64 lanes of a wave (Hillis-Steele inside each row
+// of 16 lanes, then row totals carried by row_bcast:15 / :31).  `step(v, c, m)`
+// returns v combined with the DPP-shifted v for control c and row mask m.
 template <typename T, typename Step>
 __device__ __forceinline__ T wave_scan_dpp(T v, Step step) {
-    v += step(v, std::integral_constant<int, 0x111>(), std::integral_constant<int, 0xF>());
-    v += step(v, std::integral_constant<int, 0x112>(), std::integral_constant<int, 0xF>());
-    v += step(v, std::integral_constant<int, 0x114>(), std::integral_constant<int, 0xF>());
-    v += step(v, std::integral_constant<int, 0x118>(), std::integral_constant<int, 0xF>());
-    v += step(v, std::integral_constant<int, 0x142>(), std::integral_constant<int, 0xA>());
-    v += step(v, std::integral_constant<int, 0x143>(), std::integral_constant<int, 0xC>());
+    v = step(v, std::integral_constant<int, 0x111>(), std::integral_constant<int, 0xF>());
+    v = step(v, std::integral_constant<int, 0x112>(), std::integral_constant<int, 0xF>());
+    v = step(v, std::integral_constant<int, 0x114>(), std::integral_constant<int, 0xF>());
+    v = step(v, std::integral_constant<int, 0x118>(), std::integral_constant<int, 0xF>());
+    v = step(v, std::integral_constant<int, 0x142>(), std::integral_constant<int, 0xA>());
+    v = step(v, std::integral_constant<int, 0x143>(), std::integral_constant<int, 0xC>());
     return v;
 }
 
+#define DDHF_DPP_ARGS decltype(c)::value, decltype(m)::value
+
 __device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v) {
-    return wave_scan_dpp(v, [](uint32_t x, auto c, auto m) { return dpp_u32<decltype(c)::value, decltype(m)::value>(x); });
+    return wave_scan_dpp(v, [](uint32_t x, auto c, auto m) { return x + dpp_u32<DDHF_DPP_ARGS>(x); });
 }
 
 // Sum over the 64 lanes of a wave, returned in every lane (the inclusive scan's
@@ -101,16 +104,36 @@ __device__ __forceinline__ uint32_t wave_sum(uint32_t v) {
 }
 
 __device__ __forceinline__ float wave_sum(float v) {
-    v = wave_scan_dpp(v, [](float x, auto c, auto m) { return dpp_f32<decltype(c)::value, decltype(m)::value>(x); });
+    v = wave_scan_dpp(v, [](float x, auto c, auto m) { return x + dpp_f32<DDHF_DPP_ARGS>(x); });
     return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 63));
 }
 
 __device__ __forceinline__ double wave_sum(double v) {
-    v = wave_scan_dpp(v, [](double x, auto c, auto m) { return dpp_f64<decltype(c)::value, decltype(m)::value>(x); });
+    v = wave_scan_dpp(v, [](double x, auto c, auto m) { return x + dpp_f64<DDHF_DPP_ARGS>(x); });
     const int lo = __builtin_amdgcn_readlane(__double2loint(v), 63);
     const int hi = __builtin_amdgcn_readlane(__double2hiint(v), 63);
     return __hiloint2double(hi, lo);
 }
+
+// Maximum over the 64 lanes of a wave for non-negative values (lanes shifted
+// in from outside a row read 0, the identity here), returned in every lane.
+__device__ __forceinline__ float wave_max(float v) {
+    v = wave_scan_dpp(v, [](float x, auto c, auto m) { return fmaxf(x, dpp_f32<DDHF_DPP_ARGS>(x)); });
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 63));
+}
+
+__device__ __forceinline__ uint64_t wave_max(uint64_t v) {
+    v = wave_scan_dpp(v, [](uint64_t x, auto c, auto m) -> uint64_t {
+        const uint64_t o = ((uint64_t)dpp_u32<DDHF_DPP_ARGS>((uint32_t)(x >> 32)) << 32) |
+                           dpp_u32<DDHF_DPP_ARGS>((uint32_t)x);
+        return o > x ? o : x;
+    });
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, 63);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(v >> 32), 63);
+    return ((uint64_t)hi << 32) | lo;
+}
+
+#undef DDHF_DPP_ARGS
 
 // ---- host entry points implemented in one file and used by another -------
 
