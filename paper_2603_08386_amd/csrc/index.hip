@@ -131,6 +131,11 @@ __global__ __launch_bounds__(kRadixThreads) void k_radix_hist(const uint32_t* __
     if (tid < (1 << bits)) ghist[(int64_t)tid * n_tiles + blockIdx.x] = h[tid];
 }
 
+// One tile of kRadixTile keys: ranks every key among the tile's keys of the
+// same digit (ballot match masks per wavefront, wavefront counts in LDS, so
+// the order is stable), places the tile in LDS sorted by digit, then writes it
+// out so that consecutive threads write consecutive positions of each digit's
+// run (coalesced, instead of one scattered store per key).
 __global__ __launch_bounds__(kRadixThreads) void k_radix_scatter(
     const uint32_t* __restrict__ kin, const uint32_t* __restrict__ vin,
     uint32_t* __restrict__ kout, uint32_t* __restrict__ vout, int64_t n_host,
@@ -138,6 +143,9 @@ __global__ __launch_bounds__(kRadixThreads) void k_radix_scatter(
     int n_tiles, const uint32_t* __restrict__ v2in, uint32_t* __restrict__ v2out) {
     __shared__ uint32_t cnt[kRadixWaves][256];
     __shared__ uint32_t woff[kRadixWaves][256];
+    __shared__ uint32_t doff[256];     // start of each digit's run in the tile
+    __shared__ uint32_t wsum[kRadixWaves];
+    __shared__ uint32_t sk[kRadixTile], sv[kRadixTile], sv2[kRadixTile];
     const int tid = threadIdx.x;
     const int w = tid / kWave;
     const int lane = __lane_id();
@@ -145,7 +153,8 @@ __global__ __launch_bounds__(kRadixThreads) void k_radix_scatter(
     for (int i = tid; i < kRadixWaves * 256; i += kRadixThreads) cnt[i / 256][i % 256] = 0;
     __syncthreads();
     const uint32_t mask = (1u << bits) - 1u;
-    const int64_t wbase = (int64_t)blockIdx.x * kRadixTile + (int64_t)w * kWaveSpan;
+    const int64_t tbase = (int64_t)blockIdx.x * kRadixTile;
+    const int64_t wbase = tbase + (int64_t)w * kWaveSpan;
     const uint64_t lt = lanemask_lt();
     uint32_t key[kRadixItems], val[kRadixItems], val2[kRadixItems], rank[kRadixItems];
     volatile uint32_t* wc = cnt[w];
@@ -174,13 +183,23 @@ __global__ __launch_bounds__(kRadixThreads) void k_radix_scatter(
         rank[it] = before + r;
     }
     __syncthreads();
+    // per digit: wavefront offsets and the tile total; then the digits' run
+    // starts by an exclusive scan over the 256 digits (one per thread)
+    uint32_t tot = 0;
     if (tid < 256) {
-        uint32_t s = 0;
 #pragma unroll
         for (int q = 0; q < kRadixWaves; ++q) {
-            woff[q][tid] = s;
-            s += cnt[q][tid];
+            woff[q][tid] = tot;
+            tot += cnt[q][tid];
         }
+    }
+    const uint32_t incl = wave_incl_scan(tot);
+    if (lane == kWave - 1) wsum[w] = incl;
+    __syncthreads();
+    if (tid < 256) {
+        uint32_t o = incl - tot;
+        for (int q = 0; q < w; ++q) o += wsum[q];
+        doff[tid] = o;
     }
     __syncthreads();
 #pragma unroll
@@ -188,11 +207,22 @@ __global__ __launch_bounds__(kRadixThreads) void k_radix_scatter(
         const int64_t idx = wbase + (int64_t)it * kWave + lane;
         if (idx < n) {
             const uint32_t d = (key[it] >> shift) & mask;
-            const uint32_t pos = goff[(int64_t)d * n_tiles + blockIdx.x] + woff[w][d] + rank[it];
-            kout[pos] = key[it];
-            vout[pos] = val[it];
-            if (v2out) v2out[pos] = val2[it];
+            const uint32_t lp = doff[d] + woff[w][d] + rank[it];
+            sk[lp] = key[it];
+            sv[lp] = val[it];
+            sv2[lp] = val2[it];
         }
+    }
+    __syncthreads();
+    const int64_t rem = n - tbase;
+    const int nt = rem < kRadixTile ? (int)rem : kRadixTile;
+    for (int i = tid; i < nt; i += kRadixThreads) {
+        const uint32_t k = sk[i];
+        const uint32_t d = (k >> shift) & mask;
+        const uint32_t pos = goff[(int64_t)d * n_tiles + blockIdx.x] + (uint32_t)i - doff[d];
+        kout[pos] = k;
+        vout[pos] = sv[i];
+        if (v2out) v2out[pos] = sv2[i];
     }
 }
 
