@@ -306,8 +306,9 @@ __device__ __forceinline__ MfOps mf_operands(const EvStage& s, bool upper, uint3
     o.a1 = __uint_as_float(p[1]);
     o.bre = upper ? -vs : vc;  // B real: Re V | -Im V
     o.bim = upper ? vc : vs;   // B imag: Im V | Re V
-    o.wc = s.wc;
-    o.ws = s.ws;
+    // the step phasor is the same for the whole wave: keep it in scalar registers
+    o.wc = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(s.wc)));
+    o.ws = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(s.ws)));
     return o;
 }
 
