@@ -10,9 +10,9 @@
 // Since theta_h = h theta_1 (mod 2 pi) exactly, each event needs one exact
 // phase reduction and one sin/cos; the harmonics follow by complex
 // multiplication with exp(i theta_1).
-// Forward: one wavefront per pixel, events on lanes, 2 nh accumulators per
-// lane, butterfly reduction in a fixed order.  Backward: per-event gradients
-// in the same layout; the pixel partials of dL/dw_h and dL/dtau are written
+// Forward: a row of 16 lanes per pixel (four pixels per wavefront), events on
+// the row's lanes, 2 nh accumulators per lane, fixed-order in-row reductions.
+// Backward: per-event gradients in the same layout; the pixel partials of dL/dw_h and dL/dtau are written
 // per pixel and summed in two fixed-order stages (deterministic).
 // Templated on float and double (the double instantiation serves gradcheck).
 #include "ddhf_internal.h"
@@ -25,7 +25,9 @@ template <typename T>
 __device__ __forceinline__ void sincos_rev(T rev, T& s, T& c);
 template <>
 __device__ __forceinline__ void sincos_rev<float>(float rev, float& s, float& c) {
-    sincospif(2.0f * rev, &s, &c);
+    // transcendental unit, argument in revolutions (|rev| <= 1/2)
+    s = __builtin_amdgcn_sinf(rev);
+    c = __builtin_amdgcn_cosf(rev);
 }
 template <>
 __device__ __forceinline__ void sincos_rev<double>(double rev, double& s, double& c) {
@@ -42,6 +44,25 @@ __device__ __forceinline__ T phase_rev(int64_t f, uint32_t t, T dt) {
     return (T)rev;
 }
 
+constexpr int kRow = 16;  // lanes per pixel
+
+// Sum over one row of 16 lanes (DPP row shifts, fixed order); valid in the
+// row's last lane.
+__device__ __forceinline__ float row_sum16(float v) {
+    v += dpp_f32<0x111, 0xF>(v);
+    v += dpp_f32<0x112, 0xF>(v);
+    v += dpp_f32<0x114, 0xF>(v);
+    v += dpp_f32<0x118, 0xF>(v);
+    return v;
+}
+__device__ __forceinline__ double row_sum16(double v) {
+    v += dpp_f64<0x111, 0xF>(v);
+    v += dpp_f64<0x112, 0xF>(v);
+    v += dpp_f64<0x114, 0xF>(v);
+    v += dpp_f64<0x118, 0xF>(v);
+    return v;
+}
+
 template <typename T>
 __global__ __launch_bounds__(64) void k_soft_fwd(const int32_t* __restrict__ row_ptr,
                                                  const uint32_t* __restrict__ t_rel,
@@ -53,18 +74,18 @@ __global__ __launch_bounds__(64) void k_soft_fwd(const int32_t* __restrict__ row
                                                  const T* __restrict__ tau, double beta,
                                                  T* __restrict__ s_out, T* __restrict__ phat,
                                                  T* __restrict__ F) {
-    const int32_t u = blockIdx.x;
-    if (u >= n_active) return;
-    const int lane = threadIdx.x;
-    const int32_t q = active[u];
-    const int32_t b = row_ptr[q], e = row_ptr[q + 1];
-    const int64_t fu = f0[u];
+    const int32_t u = blockIdx.x * (64 / kRow) + (int32_t)(threadIdx.x / kRow);
+    const int sl = threadIdx.x % kRow;
+    const bool has = u < n_active;  // the whole row agrees; rows stay in the wave for the DPP sums
+    const int32_t q = has ? active[u] : 0;
+    const int32_t b = has ? row_ptr[q] : 0, e = has ? row_ptr[q + 1] : 0;
+    const int64_t fu = has ? f0[u] : 0;
     T re[kMaxHarm], im[kMaxHarm];
 #pragma unroll
     for (int h = 0; h < kMaxHarm; ++h) { re[h] = (T)0; im[h] = (T)0; }
     // harmonics h + 1 with (h + 1) f0 <= f_max form a prefix
     const int hv = fu > 0 ? (int)(f_max / fu < (int64_t)nh ? f_max / fu : (int64_t)nh) : 0;
-    for (int32_t k = b + lane; k < e; k += 64) {
+    for (int32_t k = b + sl; k < e; k += kRow) {
         const uint32_t t = t_rel[k];
         const T a = sgn[k] * ew[k];
         const T d = dt[k];
@@ -83,22 +104,23 @@ __global__ __launch_bounds__(64) void k_soft_fwd(const int32_t* __restrict__ row
         }
     }
     const T n = (T)(e - b);
-    T x = -tau[0];
+    T x = has ? -tau[0] : (T)0;
+    const bool last = sl == kRow - 1;
 #pragma unroll
     for (int h = 0; h < kMaxHarm; ++h) {
         if (h < nh) {
-            const T R = wave_sum(re[h]);  // fixed-order DPP reduction
-            const T I = wave_sum(im[h]);
+            const T R = row_sum16(re[h]);  // fixed-order in-row reduction
+            const T I = row_sum16(im[h]);
             const T ph = n > (T)0 ? (R * R + I * I) / n : (T)0;
             x += w[h] * ph;
-            if (lane == 0) {
+            if (has && last) {
                 phat[(int64_t)u * nh + h] = ph;
                 F[((int64_t)u * nh + h) * 2] = R;
                 F[((int64_t)u * nh + h) * 2 + 1] = I;
             }
         }
     }
-    if (lane == 0) s_out[u] = (T)1 / ((T)1 + (T)exp(-beta * (double)x));
+    if (has && last) s_out[u] = (T)1 / ((T)1 + (T)exp(-beta * (double)x));
 }
 
 template <typename T>
@@ -113,24 +135,34 @@ __global__ __launch_bounds__(64) void k_soft_bwd(const int32_t* __restrict__ row
                                                  const T* __restrict__ F, const T* __restrict__ g_s,
                                                  T* __restrict__ g_e, T* __restrict__ g_dt,
                                                  T* __restrict__ part /*[n_active][nh + 1]*/) {
-    const int32_t u = blockIdx.x;
+    const int32_t u = blockIdx.x * (64 / kRow) + (int32_t)(threadIdx.x / kRow);
     if (u >= n_active) return;
-    const int lane = threadIdx.x;
+    const int sl = threadIdx.x % kRow;
     const int32_t q = active[u];
     const int32_t b = row_ptr[q], e = row_ptr[q + 1];
     const int64_t fu = f0[u];
     const T su = s[u];
     const T gx = g_s[u] * (T)beta * su * ((T)1 - su);
     const T n = (T)(e - b);
-    if (lane <= nh) {
-        T v;
-        if (lane < nh) v = gx * phat[(int64_t)u * nh + lane];
-        else v = -gx;
-        part[(int64_t)u * (nh + 1) + lane] = v;
+    for (int j = sl; j <= nh; j += kRow) {
+        const T v = j < nh ? gx * phat[(int64_t)u * nh + j] : -gx;
+        part[(int64_t)u * (nh + 1) + j] = v;
     }
     const int hv = fu > 0 ? (int)(f_max / fu < (int64_t)nh ? f_max / fu : (int64_t)nh) : 0;
     const T tw = (T)(2.0 * M_PI * (double)fu * 1e-9);  // d theta_1 / d dt (per us)
-    for (int32_t k = b + lane; k < e; k += 64) {
+    // per harmonic: gP_h F_h with gP_h = dL/dP^_h / n (pixel constants)
+    T cr[kMaxHarm], ci[kMaxHarm];
+#pragma unroll
+    for (int h = 0; h < kMaxHarm; ++h) {
+        cr[h] = (T)0;
+        ci[h] = (T)0;
+        if (h < hv) {
+            const T gP = gx * w[h] / n;
+            cr[h] = gP * F[((int64_t)u * nh + h) * 2];
+            ci[h] = gP * F[((int64_t)u * nh + h) * 2 + 1];
+        }
+    }
+    for (int32_t k = b + sl; k < e; k += kRow) {
         const uint32_t t = t_rel[k];
         const T p = sgn[k];
         const T ek = ew[k];
@@ -138,22 +170,19 @@ __global__ __launch_bounds__(64) void k_soft_bwd(const int32_t* __restrict__ row
         T s1, c1;
         sincos_rev<T>(phase_rev<T>(fu, t, d), s1, c1);
         T zc = c1, zs = s1;
-        T ge = (T)0, gd = (T)0;
+        T sr = (T)0, si = (T)0;  // sum_h gP_h Re / Im(conj(F_h) e^{i theta_h}), the latter times h+1
 #pragma unroll
         for (int h = 0; h < kMaxHarm; ++h) {
             if (h < hv) {
-                const T Fr = F[((int64_t)u * nh + h) * 2];
-                const T Fi = F[((int64_t)u * nh + h) * 2 + 1];
-                const T gP = gx * w[h] / n;
-                const T rp = Fr * zc + Fi * zs;   // Re(conj(F) e^{i theta})
-                const T ip = Fr * zs - Fi * zc;   // Im(conj(F) e^{i theta})
-                ge += gP * (T)2 * p * rp;
-                gd += gP * ((T)-2 * p * ek * ip) * (tw * (T)(h + 1));
+                sr += cr[h] * zc + ci[h] * zs;
+                si += (T)(h + 1) * (cr[h] * zs - ci[h] * zc);
                 const T nc = zc * c1 - zs * s1;
                 zs = zc * s1 + zs * c1;
                 zc = nc;
             }
         }
+        const T ge = (T)2 * p * sr;
+        const T gd = (T)-2 * p * ek * si * tw;
         g_e[k] = ge;
         g_dt[k] = gd;
     }
@@ -227,12 +256,12 @@ extern "C" int ddhf_soft_comb_forward(const int32_t* row_ptr, const uint32_t* t_
         return DDHF_EINVAL;
     hipStream_t s = as_stream(stream);
     if (dtype == 0)
-        hipLaunchKernelGGL(k_soft_fwd<float>, dim3(n_active), dim3(64), 0, s, row_ptr, t_rel,
+        hipLaunchKernelGGL(k_soft_fwd<float>, dim3((n_active + 3) / 4), dim3(64), 0, s, row_ptr, t_rel,
                            (const float*)sgn, (const float*)e, (const float*)dt, active, n_active,
                            f0_mhz, nh, f_max_mhz, (const float*)w, (const float*)tau, beta,
                            (float*)s_out, (float*)phat_out, (float*)F_out);
     else
-        hipLaunchKernelGGL(k_soft_fwd<double>, dim3(n_active), dim3(64), 0, s, row_ptr, t_rel,
+        hipLaunchKernelGGL(k_soft_fwd<double>, dim3((n_active + 3) / 4), dim3(64), 0, s, row_ptr, t_rel,
                            (const double*)sgn, (const double*)e, (const double*)dt, active,
                            n_active, f0_mhz, nh, f_max_mhz, (const double*)w, (const double*)tau,
                            beta, (double*)s_out, (double*)phat_out, (double*)F_out);
@@ -269,13 +298,13 @@ extern "C" int ddhf_soft_comb_backward(const int32_t* row_ptr, const uint32_t* t
             !F || !g_s || !g_e || !g_dt)
             return DDHF_EINVAL;
         if (dtype == 0)
-            hipLaunchKernelGGL(k_soft_bwd<float>, dim3(n_active), dim3(64), 0, st, row_ptr, t_rel,
+            hipLaunchKernelGGL(k_soft_bwd<float>, dim3((n_active + 3) / 4), dim3(64), 0, st, row_ptr, t_rel,
                                (const float*)sgn, (const float*)e, (const float*)dt, active,
                                n_active, f0_mhz, nh, f_max_mhz, (const float*)w, beta,
                                (const float*)s, (const float*)phat, (const float*)F,
                                (const float*)g_s, (float*)g_e, (float*)g_dt, (float*)ws);
         else
-            hipLaunchKernelGGL(k_soft_bwd<double>, dim3(n_active), dim3(64), 0, st, row_ptr,
+            hipLaunchKernelGGL(k_soft_bwd<double>, dim3((n_active + 3) / 4), dim3(64), 0, st, row_ptr,
                                t_rel, (const double*)sgn, (const double*)e, (const double*)dt,
                                active, n_active, f0_mhz, nh, f_max_mhz, (const double*)w, beta,
                                (const double*)s, (const double*)phat, (const double*)F,
