@@ -24,11 +24,12 @@ constexpr int kHistBins = 2048;
 
 struct CombArgs {
     int32_t K, M, dk, h_min;
-    int64_t f0, df;
-    int64_t g;        // f0 / df when df divides f0, else -1
     float eps;
     int32_t b_lo, b_hi;
     int32_t kpad;     // K rounded up to a multiple of 4
+    // Harmonic m of candidate bin i is centred on bin m i + off[m - 1]: the
+    // centre ((m - 1) f0 + m i df) / df rounded half up, and m i is an integer.
+    int32_t off[32];
 };
 
 template <int NT = kCombThreads>
@@ -236,11 +237,7 @@ __global__ __launch_bounds__(kCombThreads) void k_comb(const float* __restrict__
     int best_i = -1;
     for (int i = tid; i < K; i += kCombThreads) {
         // harmonic centre of window m (1-based), rounded half up
-        auto centre = [&](int m) -> int64_t {
-            if (ca.g >= 0) return (int64_t)(m - 1) * ca.g + (int64_t)m * i;
-            const double num = (double)(m - 1) * (double)ca.f0 + (double)m * (double)i * (double)ca.df;
-            return (int64_t)floor(num / (double)ca.df + 0.5);
-        };
+        auto centre = [&](int m) -> int64_t { return (int64_t)m * i + ca.off[m - 1]; };
         int mv = 0;
         for (int m = 1; m <= ca.M; ++m) {
             const int64_t cm = centre(m);
@@ -407,12 +404,22 @@ __device__ __forceinline__ void locate_x2(const uint32_t* h1, uint32_t base1, in
         r1 += k < w ? scr[k] : 0u;
         r2 += k < w ? scr[kFT / kWave + k] : 0u;
     }
+    // only the thread whose buckets hold a target walks them (0 <= tgt < total)
+    if ((uint32_t)tgt1 - r1 < s1) {
+        uint32_t r = r1;
 #pragma unroll
-    for (int i = 0; i < 8; ++i) {
-        if ((int64_t)r1 <= tgt1 && tgt1 < (int64_t)(r1 + c1[i])) { out1->d = tid * 8 + i; out1->before = r1; }
-        if ((int64_t)r2 <= tgt2 && tgt2 < (int64_t)(r2 + c2[i])) { out2->d = tid * 8 + i; out2->before = r2; }
-        r1 += c1[i];
-        r2 += c2[i];
+        for (int i = 0; i < 8; ++i) {
+            if ((uint32_t)tgt1 - r < c1[i]) { out1->d = tid * 8 + i; out1->before = r; }
+            r += c1[i];
+        }
+    }
+    if ((uint32_t)tgt2 - r2 < s2) {
+        uint32_t r = r2;
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+            if ((uint32_t)tgt2 - r < c2[i]) { out2->d = tid * 8 + i; out2->before = r; }
+            r += c2[i];
+        }
     }
     __syncthreads();
 }
@@ -495,11 +502,21 @@ __global__ __launch_bounds__(kFT) void k_comb_fast(const float* __restrict__ pow
     for (int i = 0; i < kXWords / kFT; ++i) sX[tid + i * kFT] = 0u;
     __syncthreads();
     // ---- log-sum (Eq. 7) and second digit (bits 10..19) ---------------------
-    double sl = 0.0;
+    // log2 terms summed pairwise in FP32 within the segment (16 terms, error
+    // a few ulps of the segment sum), then across segments in FP64
+    float lg[kFastItems];
+#pragma unroll
+    for (int j = 0; j < kFastItems; ++j)
+        lg[j] = j < nmine ? __log2f(v[j] > floor_v ? v[j] : floor_v) : 0.0f;
+#pragma unroll
+    for (int h = kFastItems / 2; h >= 1; h >>= 1) {
+#pragma unroll
+        for (int j = 0; j < h; ++j) lg[j] += lg[j + h];
+    }
+    double sl = (double)lg[0];
 #pragma unroll
     for (int j = 0; j < kFastItems; ++j) {
         if (j < nmine) {
-            sl += (double)__log2f(v[j] > floor_v ? v[j] : floor_v);
             const uint32_t b = __float_as_uint(v[j]);
             const uint32_t d1 = (b >> 20) & 0x7FFu;
             const int d2 = pad8((int)((b >> 10) & 0x3FFu));
@@ -508,7 +525,18 @@ __global__ __launch_bounds__(kFT) void k_comb_fast(const float* __restrict__ pow
         }
     }
     sl = block_sum_d<kFT>(sl, red);
-    if (tid == 0) sf_out[u] = mean > 0.0 ? (float)exp2(sl / (double)K - log2(mean)) : 1.0f;
+    if (tid == 0) {
+        // log2(mean) = e + log2(m), m in [0.5, 1): the FP32 logarithm of the
+        // mantissa keeps the exponent difference accurate to ~1e-7
+        float f = 1.0f;
+        if (mean > 0.0) {
+            int e = 0;
+            const double m = frexp(mean, &e);
+            const double lm = (double)e + (double)__log2f((float)m);
+            f = exp2f((float)(sl / (double)K - lm));
+        }
+        sf_out[u] = f;
+    }
     locate_x2<kH2, false>(h2lo, l1lo.before, ca.b_lo, &l2lo, h2hi, l1hi.before, ca.b_hi, &l2hi,
                           scr);
     const uint32_t key_lo = (d1lo << 10) | (uint32_t)l2lo.d;
@@ -627,11 +655,7 @@ __global__ __launch_bounds__(kFT) void k_comb_fast(const float* __restrict__ pow
     const int bw = ca.b_hi - ca.b_lo;
     float best = 0.0f;
     int best_i = -1;
-    auto centre_of = [&](int i, int m) -> int {
-        if (ca.g >= 0) return m * ((int)ca.g + i) - (int)ca.g;
-        const double num = (double)(m - 1) * (double)ca.f0 + (double)m * (double)i * (double)ca.df;
-        return (int)floor(num / (double)ca.df + 0.5);
-    };
+    auto centre_of = [&](int i, int m) -> int { return m * i + ca.off[m - 1]; };
     // harmonics whose window stays inside [0, K)
     auto n_valid = [&](int i) -> int {
         int mv = 0;
@@ -732,6 +756,13 @@ __global__ __launch_bounds__(kFT) void k_comb_fast(const float* __restrict__ pow
         // (centres grow with m, so the valid harmonics are a prefix; the
         // reciprocal is approximate, which the bounds' margin covers)
         auto n_of = [&](int i) -> float {
+            if (MT > 0 && centre_of(i, MT) + dk <= K - 1) {
+                // every harmonic's window is inside the spectrum (centres grow with m)
+                float smax = 0.0f;
+#pragma unroll
+                for (int m = 1; m <= (MT > 0 ? MT : 1); ++m) smax += sP[padk(centre_of(i, m))];
+                return MT >= ca.h_min ? smax * (1.0f / (float)(MT > 0 ? MT : 1)) : -1.0f;
+            }
             int mv = 0;
             float smax = 0.0f;
 #pragma unroll
@@ -826,9 +857,11 @@ int comb_run(const float* power, int32_t n_active, const int32_t* n_dev, const d
     ca.M = prm->M;
     ca.dk = prm->dk;
     ca.h_min = prm->h_min;
-    ca.f0 = grid->f0;
-    ca.df = grid->df;
-    ca.g = (grid->f0 % grid->df == 0) ? grid->f0 / grid->df : -1;
+    for (int m = 1; m <= 32; ++m) {
+        const int64_t num = (int64_t)(m - 1) * grid->f0;  // >= 0
+        int64_t o = num % grid->df == 0 ? num / grid->df : (2 * num + grid->df) / (2 * grid->df);
+        ca.off[m - 1] = (int32_t)(o < (1 << 30) ? o : (1 << 30));  // beyond any bin
+    }
     ca.eps = prm->eps_rel;
     const int hmax = prm->M * (2 * prm->dk + 1);
     int b_lo = (ca.K - hmax - 1) / 2;
@@ -840,8 +873,8 @@ int comb_run(const float* power, int32_t n_active, const int32_t* n_dev, const d
     ca.kpad = (ca.K + 3) / 4 * 4;
     // largest candidate whose first h_min windows stay in band (centres grow with i)
     auto centre_h = [&](int64_t m, int64_t i) -> int64_t {
-        const int64_t num = (m - 1) * ca.f0 + m * i * ca.df;
-        return num % ca.df == 0 ? num / ca.df : (2 * num + ca.df) / (2 * ca.df);
+        const int64_t num = (m - 1) * grid->f0 + m * i * grid->df;
+        return num % grid->df == 0 ? num / grid->df : (2 * num + grid->df) / (2 * grid->df);
     };
     int32_t i_max = -1;
     {
