@@ -352,44 +352,74 @@ constexpr int kFT = 256;           // threads per pixel
 constexpr int kFastItems = 16;     // bins per thread: K <= 4096
 constexpr int kSegShift = 4;       // log2(kFastItems)
 static_assert(kFT * kFastItems == 4096 && (1 << kSegShift) == kFastItems, "fast comb shape");
-constexpr int kListCap = 512;
+constexpr int kListCap = 256;
 constexpr int kInbCap = 8;         // in-band window bins kept in registers per candidate
-constexpr int kXWords = 2304;      // histogram / code region (words)
-constexpr int kH1 = 2048;          // level-1 buckets (bits 20..30)
-constexpr int kH2 = 1024;          // level-2 buckets (bits 10..19)
-constexpr int kCodeBytes = 4352;   // padk(4095) + 1, rounded
-constexpr int kListOff = kCodeBytes;                 // byte offset of the candidate list
-constexpr int kBandOff = kListOff + 2 * kListCap;    // byte offset of the band values
-static_assert(kBandOff + 4 * 256 <= 4 * kXWords, "fast comb LDS region");
+constexpr int kHistWords = 1280;   // 1024 packed words + pad8, rounded to 5 x 256
 constexpr uint8_t kCodeCand = 0xFDu, kCodeBelow = 0xFEu, kCodeAbove = 0xFFu;
 
 // one padding slot after every thread segment
 __device__ __forceinline__ int padk(int k) { return k + (k >> kSegShift); }
 __device__ __forceinline__ int pad8(int b) { return b + (b >> 3); }
+// After the histograms the same region holds one code byte per bin (padded
+// like the spectrum), the candidate list and the band values.
+__host__ __device__ constexpr int code_bytes(int K) {
+    return ((K - 1) + ((K - 1) >> kSegShift) + 1 + 3) / 4 * 4;
+}
+__host__ __device__ constexpr int x_bytes(int K, int band) {
+    const int codes = code_bytes(K) + 2 * kListCap + 4 * band;
+    return ((codes > 4 * kHistWords ? codes : 4 * kHistWords) + 15) / 16 * 16;
+}
 
 struct Loc {
     int d;
     uint32_t before;
 };
 
-// Bucket of rank tgt in a padded histogram of NB buckets (8 per thread for
-// the first NB / 8 threads; `base` elements counted before it); one thread
-// writes `out`.  Two histograms / targets share the barriers.
-template <int NB, bool SAME>
-__device__ __forceinline__ void locate_x2(const uint32_t* h1, uint32_t base1, int32_t tgt1,
-                                          Loc* out1, const uint32_t* h2, uint32_t base2,
-                                          int32_t tgt2, Loc* out2, uint32_t* scr) {
+// Per-segment loops run with compile-time bounds for threads whose 16 bins
+// all lie inside [0, K) (every wave except the one holding bin K - 1), and
+// with a bounds test per bin otherwise.
+template <class F>
+__device__ __forceinline__ void seg_dispatch(int nmine, F&& f) {
+    if (nmine == kFastItems) f(std::true_type{});
+    else f(std::false_type{});
+}
+#define DDHF_IN_SEG(full, j) (decltype(full)::value || (j) < nmine)
+
+// Histograms hold 16-bit counters, two per word (a count never exceeds
+// K <= 4096), in 1024 words padded by one per 8 (pad8):
+//   level 1: bucket d (bits 20..30 of the value) in half d >> 10 of word d & 1023;
+//   level 2: bucket d (bits 10..19) of the low-end histogram in the low half and
+//            of the high-end histogram in the high half of word d.
+// locate_x2 finds, for two target ranks, the bucket holding each and the number
+// of elements before it (`base` counted before the histogram); a scan thread
+// owns 8 consecutive buckets, and the owner of a target writes its Loc.
+template <int LEVEL>
+__device__ __forceinline__ void locate_x2(const uint32_t* h, uint32_t base1, int32_t tgt1,
+                                          Loc* out1, uint32_t base2, int32_t tgt2, Loc* out2,
+                                          uint32_t* scr) {
     const int tid = threadIdx.x;
-    const bool own = tid < NB / 8;
     uint32_t c1[8], c2[8];
     uint32_t s1 = 0, s2 = 0;
+    if (LEVEL == 1) {
+        const int w0 = 9 * (tid & 127), sh = (tid >> 7) << 4;  // 256 owners x 8 buckets
 #pragma unroll
-    for (int i = 0; i < 8; ++i) {
-        c1[i] = own ? h1[tid * 9 + i] : 0u;
-        c2[i] = SAME ? c1[i] : (own ? h2[tid * 9 + i] : 0u);
-        s1 += c1[i];
-        s2 += c2[i];
+        for (int i = 0; i < 8; ++i) {
+            c1[i] = c2[i] = (h[w0 + i] >> sh) & 0xFFFFu;
+            s1 += c1[i];
+        }
+        s2 = s1;
+    } else {
+        const bool own = tid < 128;  // 128 owners x 8 buckets
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+            const uint32_t wv = own ? h[9 * tid + i] : 0u;
+            c1[i] = wv & 0xFFFFu;
+            c2[i] = wv >> 16;
+            s1 += c1[i];
+            s2 += c2[i];
+        }
     }
+    constexpr bool SAME = LEVEL == 1;
     const uint32_t i1 = wave_incl_scan(s1);
     const uint32_t i2 = SAME ? i1 : wave_incl_scan(s2);
     const int w = tid / kWave;
@@ -434,10 +464,10 @@ __global__ __launch_bounds__(kFT) void k_comb_fast(const float* __restrict__ pow
                                                    const int32_t* __restrict__ n_dev) {
     extern __shared__ __align__(16) char smem[];
     float* sP = (float*)smem;                       // [kpad]: spectrum, then window maxima
-    uint32_t* sX = (uint32_t*)(sP + ca.kpad);       // [kXWords]: histograms, then codes ...
-    uint8_t* sCode = (uint8_t*)sX;                  // [kCodeBytes] one code per bin
-    uint16_t* sList = (uint16_t*)((char*)sX + kListOff);  // [kListCap] candidates / queue
-    float* sBand = (float*)((char*)sX + kBandOff);  // [256] band values in rank order
+    uint32_t* sX = (uint32_t*)(sP + ca.kpad);       // histograms, then codes ...
+    uint8_t* sCode = (uint8_t*)sX;                  // [code_bytes(K)] one code per bin
+    uint16_t* sList = (uint16_t*)((char*)sX + code_bytes(ca.K));  // [kListCap] candidates
+    float* sBand = (float*)((char*)sX + code_bytes(ca.K) + 2 * kListCap);  // band values
     __shared__ double red[kFT / kWave];
     __shared__ uint32_t scr[2 * kFT / kWave];
     __shared__ Loc l1lo, l1hi, l2lo, l2hi;
@@ -452,8 +482,6 @@ __global__ __launch_bounds__(kFT) void k_comb_fast(const float* __restrict__ pow
     const int32_t u = blockIdx.x;
     if (u >= n_active || (n_dev && u >= *n_dev)) return;
     const float* row = power + (int64_t)u * K;
-    uint32_t* h2lo = sX;
-    uint32_t* h2hi = sX + kXWords / 2;
     const int k0 = tid * kFastItems;        // first bin of this thread's segment
     const int s0 = tid * (kFastItems + 1);  // its padded LDS index
 
@@ -466,7 +494,7 @@ __global__ __launch_bounds__(kFT) void k_comb_fast(const float* __restrict__ pow
             g[i] = k < K ? row[k] : 0.0f;
         }
 #pragma unroll
-        for (int i = 0; i < kXWords / kFT; ++i) sX[tid + i * kFT] = 0u;
+        for (int i = 0; i < kHistWords / kFT; ++i) sX[tid + i * kFT] = 0u;
         if (tid == 0) {
             l1lo = l1hi = l2lo = l2hi = Loc{0, 0};
             s_nlist = 0;
@@ -481,49 +509,53 @@ __global__ __launch_bounds__(kFT) void k_comb_fast(const float* __restrict__ pow
     float v[kFastItems];
     int nmine = K - k0;  // bins of this segment inside [0, K)
     nmine = nmine < 0 ? 0 : (nmine > kFastItems ? kFastItems : nmine);
-#pragma unroll
-    for (int j = 0; j < kFastItems; ++j) v[j] = j < nmine ? sP[s0 + j] : 0.0f;
-
     // ---- sum and first digit (bits 20..30) ----------------------------------
     float fsum = 0.0f;  // 16 terms per thread; the block sum is in FP64
+    seg_dispatch(nmine, [&](auto full) {
 #pragma unroll
-    for (int j = 0; j < kFastItems; ++j) {
-        if (j < nmine) {
-            fsum += v[j];
-            atomicAdd(&sX[pad8((int)((__float_as_uint(v[j]) >> 20) & 0x7FFu))], 1u);
+        for (int j = 0; j < kFastItems; ++j) v[j] = DDHF_IN_SEG(full, j) ? sP[s0 + j] : 0.0f;
+#pragma unroll
+        for (int j = 0; j < kFastItems; ++j) {
+            if (DDHF_IN_SEG(full, j)) {
+                fsum += v[j];
+                const uint32_t b = __float_as_uint(v[j]);
+                atomicAdd(&sX[pad8((int)((b >> 20) & 0x3FFu))], 1u << ((b >> 26) & 16u));
+            }
         }
-    }
+    });
     const double sum = block_sum_d<kFT>((double)fsum, red);
     const double mean = sum / (double)K;
     const float floor_v = (float)(ca.eps * mean);
-    locate_x2<kH1, true>(sX, 0, ca.b_lo, &l1lo, sX, 0, ca.b_hi, &l1hi, scr);
+    locate_x2<1>(sX, 0, ca.b_lo, &l1lo, 0, ca.b_hi, &l1hi, scr);
     const uint32_t d1lo = (uint32_t)l1lo.d, d1hi = (uint32_t)l1hi.d;
 #pragma unroll
-    for (int i = 0; i < kXWords / kFT; ++i) sX[tid + i * kFT] = 0u;
+    for (int i = 0; i < kHistWords / kFT; ++i) sX[tid + i * kFT] = 0u;
     __syncthreads();
     // ---- log-sum (Eq. 7) and second digit (bits 10..19) ---------------------
     // log2 terms summed pairwise in FP32 within the segment (16 terms, error
     // a few ulps of the segment sum), then across segments in FP64
     float lg[kFastItems];
+    seg_dispatch(nmine, [&](auto full) {
 #pragma unroll
-    for (int j = 0; j < kFastItems; ++j)
-        lg[j] = j < nmine ? __log2f(v[j] > floor_v ? v[j] : floor_v) : 0.0f;
+        for (int j = 0; j < kFastItems; ++j)
+            lg[j] = DDHF_IN_SEG(full, j) ? __log2f(v[j] > floor_v ? v[j] : floor_v) : 0.0f;
+#pragma unroll
+        for (int j = 0; j < kFastItems; ++j) {
+            if (DDHF_IN_SEG(full, j)) {
+                const uint32_t b = __float_as_uint(v[j]);
+                const uint32_t d1 = (b >> 20) & 0x7FFu;
+                const int d2 = pad8((int)((b >> 10) & 0x3FFu));
+                if (d1 == d1lo) atomicAdd(&sX[d2], 1u);
+                if (d1 == d1hi) atomicAdd(&sX[d2], 1u << 16);
+            }
+        }
+    });
 #pragma unroll
     for (int h = kFastItems / 2; h >= 1; h >>= 1) {
 #pragma unroll
         for (int j = 0; j < h; ++j) lg[j] += lg[j + h];
     }
     double sl = (double)lg[0];
-#pragma unroll
-    for (int j = 0; j < kFastItems; ++j) {
-        if (j < nmine) {
-            const uint32_t b = __float_as_uint(v[j]);
-            const uint32_t d1 = (b >> 20) & 0x7FFu;
-            const int d2 = pad8((int)((b >> 10) & 0x3FFu));
-            if (d1 == d1lo) atomicAdd(&h2lo[d2], 1u);
-            if (d1 == d1hi) atomicAdd(&h2hi[d2], 1u);
-        }
-    }
     sl = block_sum_d<kFT>(sl, red);
     if (tid == 0) {
         // log2(mean) = e + log2(m), m in [0.5, 1): the FP32 logarithm of the
@@ -537,24 +569,27 @@ __global__ __launch_bounds__(kFT) void k_comb_fast(const float* __restrict__ pow
         }
         sf_out[u] = f;
     }
-    locate_x2<kH2, false>(h2lo, l1lo.before, ca.b_lo, &l2lo, h2hi, l1hi.before, ca.b_hi, &l2hi,
+    locate_x2<2>(sX, l1lo.before, ca.b_lo, &l2lo, l1hi.before, ca.b_hi, &l2hi,
                           scr);
     const uint32_t key_lo = (d1lo << 10) | (uint32_t)l2lo.d;
     const uint32_t key_hi = (d1hi << 10) | (uint32_t)l2hi.d;
     const uint32_t below_base = l2lo.before;  // values with a 21-bit key below key_lo
     // ---- classify: below / above / candidate (histograms are dead now) ------
+    seg_dispatch(nmine, [&](auto full) {
 #pragma unroll
-    for (int j = 0; j < kFastItems; ++j) {
-        if (j < nmine) {
-            const uint32_t kk = (__float_as_uint(v[j]) >> 10) & 0x1FFFFFu;
-            const uint8_t code = kk < key_lo ? kCodeBelow : (kk > key_hi ? kCodeAbove : kCodeCand);
-            if (code == kCodeCand) {
-                const uint32_t pos = atomicAdd(&s_nlist, 1u);
-                if (pos < kListCap) sList[pos] = (uint16_t)(k0 + j);
+        for (int j = 0; j < kFastItems; ++j) {
+            if (DDHF_IN_SEG(full, j)) {
+                const uint32_t kk = (__float_as_uint(v[j]) >> 10) & 0x1FFFFFu;
+                const uint8_t code =
+                    kk < key_lo ? kCodeBelow : (kk > key_hi ? kCodeAbove : kCodeCand);
+                if (code == kCodeCand) {
+                    const uint32_t pos = atomicAdd(&s_nlist, 1u);
+                    if (pos < kListCap) sList[pos] = (uint16_t)(k0 + j);
+                }
+                sCode[s0 + j] = code;
             }
-            sCode[s0 + j] = code;
         }
-    }
+    });
     __syncthreads();
     // ---- exact ranks of the candidates by (value, bin) ----------------------
     const int nL = (int)s_nlist;
@@ -645,9 +680,11 @@ __global__ __launch_bounds__(kFT) void k_comb_fast(const float* __restrict__ pow
             }
         }
         __syncthreads();  // every read of the spectrum is done; codes and band are complete
+        seg_dispatch(nmine, [&](auto full) {
 #pragma unroll
-        for (int j = 0; j < kFastItems; ++j)
-            if (j < nmine) sP[s0 + j] = wm[j];
+            for (int j = 0; j < kFastItems; ++j)
+                if (DDHF_IN_SEG(full, j)) sP[s0 + j] = wm[j];
+        });
     }
     __syncthreads();
     // ---- candidates (Eq. 8-11) ----------------------------------------------
@@ -750,7 +787,11 @@ __global__ __launch_bounds__(kFT) void k_comb_fast(const float* __restrict__ pow
     // largest lower bound can be the argmax.
     const float den_lo = fmaxf(sBand[0], fden_floor);
     const float den_hi = fmaxf(sBand[bw], fden_floor);
-    if (snr_all == nullptr && den_lo > 0.0f) {
+    // candidates to evaluate exactly: the pruned list, or all of dk..i_max when
+    // every score is requested, the bounds are void or the list overflowed
+    bool every = snr_all != nullptr || !(den_lo > 0.0f);
+    int n_eval = 0;
+    if (!every) {
         const float r_hi = 1.0f / den_hi, r_lo = 1.0f / den_lo;
         // N of candidate i (the value the exact evaluation uses), -1 if inadmissible
         // (centres grow with m, so the valid harmonics are a prefix; the
@@ -798,19 +839,18 @@ __global__ __launch_bounds__(kFT) void k_comb_fast(const float* __restrict__ pow
             if (n >= 0.0f && n * r_lo >= thr) {
                 const uint32_t pos = atomicAdd(&s_qn, 1u);
                 if (pos < kListCap) sList[pos] = (uint16_t)i;
-                else eval_exact(i);
             }
         };
 #pragma unroll
         for (int r = 0; r < kKeep; ++r) offer(dk + tid + r * kFT, nv[r]);
         for (int i = dk + tid + kKeep * kFT; i <= i_max; i += kFT) offer(i, n_of(i));
         __syncthreads();
-        const int nq = (int)(s_qn < (uint32_t)kListCap ? s_qn : (uint32_t)kListCap);
-        for (int e = tid; e < nq; e += kFT) eval_exact((int)sList[e]);
-        __syncthreads();  // s_best is reused by the final reduction
-    } else {
-        for (int i = dk + tid; i <= i_max; i += kFT) eval_exact(i);
+        n_eval = (int)s_qn;
+        if (n_eval > kListCap) every = true;  // uniform
     }
+    if (every) n_eval = i_max - dk + 1;
+    // one inlined copy of the exact evaluation serves both forms
+    for (int e = tid; e < n_eval; e += kFT) eval_exact(every ? dk + e : (int)sList[e]);
     if (snr_all) {
         for (int i = tid; i < K; i += kFT)
             if (i < dk || i > i_max) snr_all[(int64_t)u * K + i] = 0.0f;
@@ -820,7 +860,7 @@ __global__ __launch_bounds__(kFT) void k_comb_fast(const float* __restrict__ pow
     uint64_t bk = best_i < 0 ? 0ull
                              : (((uint64_t)__float_as_uint(best) << 32) |
                                 (uint64_t)(0xFFFFFFFFu - (uint32_t)best_i));
-    bk = wave_max(bk);
+    if (__builtin_amdgcn_ballot_w64(best_i >= 0) != 0ull) bk = wave_max(bk);  // else all 0
     if (__lane_id() == 0) s_key[tid / kWave] = bk;
     __syncthreads();
     if (tid == 0) {
@@ -890,7 +930,7 @@ int comb_run(const float* power, int32_t n_active, const int32_t* n_dev, const d
     if (ca.K <= 4096 && bw <= 253) {
         CombArgs cf = ca;
         cf.kpad = ((ca.K - 1) + ((ca.K - 1) >> kSegShift) + 1 + 3) / 4 * 4;  // padded bin array
-        const size_t lds = (size_t)cf.kpad * 4 + (size_t)kXWords * 4;
+        const size_t lds = (size_t)cf.kpad * 4 + (size_t)x_bytes(ca.K, bw);
         const dim3 gr((unsigned)n_active), bl(kFT);
         if (ca.M == 4 && ca.dk == 3)
             hipLaunchKernelGGL((k_comb_fast<4, 3>), gr, bl, lds, s, power, n_active, cf, i_max, sf,
