@@ -474,6 +474,7 @@ __global__ __launch_bounds__(kFT) void k_comb_fast(const float* __restrict__ pow
     __shared__ uint32_t s_nlist, s_qn;
     __shared__ float s_best[kFT / kWave];
     __shared__ uint64_t s_key[kFT / kWave];
+    __shared__ uint32_t s_rank[kWave];
 
     const int K = ca.K;
     const int M = MT > 0 ? MT : ca.M;
@@ -495,6 +496,7 @@ __global__ __launch_bounds__(kFT) void k_comb_fast(const float* __restrict__ pow
         }
 #pragma unroll
         for (int i = 0; i < kHistWords / kFT; ++i) sX[tid + i * kFT] = 0u;
+        if (tid < kWave) s_rank[tid] = 0u;
         if (tid == 0) {
             l1lo = l1hi = l2lo = l2hi = Loc{0, 0};
             s_nlist = 0;
@@ -602,19 +604,24 @@ __global__ __launch_bounds__(kFT) void k_comb_fast(const float* __restrict__ pow
         sCode[padk(ki)] = code;
     };
     if (nL <= kWave) {
-        // one wavefront: candidate b's (value, bin) broadcast by readlane
-        if (tid < kWave) {
-            const bool mine = tid < nL;
-            const int ki = mine ? (int)sList[tid] : 0;
-            const float vi = mine ? sP[padk(ki)] : 0.0f;
-            uint32_t r = 0;
-            for (int b = 0; b < nL; ++b) {
-                const float vj = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(vi), b));
-                const int kj = __builtin_amdgcn_readlane(ki, b);
-                r += (vj < vi || (vj == vi && kj < ki)) ? 1u : 0u;
-            }
-            if (mine) set_rank(ki, vi, r);
+        // lane l of every wavefront holds candidate l; wave w counts the
+        // candidates of a quarter of the list (broadcast by readlane) that
+        // precede it, and the four partial counts meet in s_rank
+        const int lane = __lane_id(), w = tid / kWave;
+        const bool mine = lane < nL;
+        const int ki = mine ? (int)sList[lane] : 0;
+        const float vi = mine ? sP[padk(ki)] : 0.0f;
+        const int q = (nL + kFT / kWave - 1) / (kFT / kWave);
+        const int b1 = (w + 1) * q < nL ? (w + 1) * q : nL;
+        uint32_t r = 0;
+        for (int b = w * q; b < b1; ++b) {
+            const float vj = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(vi), b));
+            const int kj = __builtin_amdgcn_readlane(ki, b);
+            r += (vj < vi || (vj == vi && kj < ki)) ? 1u : 0u;
         }
+        if (mine && r) atomicAdd(&s_rank[lane], r);
+        __syncthreads();
+        if (tid < kWave && mine) set_rank(ki, vi, s_rank[lane]);
     } else if (nL <= kListCap) {
         for (int a = tid; a < nL; a += kFT) {
             const int ki = sList[a];
