@@ -241,7 +241,11 @@ def test_comb_random_spectra_many_shapes():
                                    (4096, 4, 3, 4, 10_000, 1000),      # largest fast-path K
                                    (5000, 4, 3, 4, 10_000, 1000),      # general kernel: K > 4096
                                    (2000, 32, 8, 4, 10_000, 500),      # general kernel: wide band
-                                   (600, 4, 6, 3, 10_000, 500)]:       # runtime window width
+                                   (600, 4, 6, 3, 10_000, 500),        # runtime window width
+                                   # grid ratios f0 / df that are not integers: harmonic
+                                   # centres round half up
+                                   (2500, 5, 3, 3, 1234, 1000), (1500, 4, 2, 3, 10_250, 1000),
+                                   (777, 3, 3, 2, 333, 7)]:
         grid = Grid(f0=f0, df=df, K=K)
         prm = Params(M=M, dk=dk, h_min=hmin)
         P = rng.exponential(size=(6, K)).astype(np.float32)
