@@ -344,9 +344,11 @@ __global__ __launch_bounds__(kCombThreads) void k_comb(const float* __restrict__
 //      can be the argmax; they alone get the exact median, from their window
 //      bins' codes: q = smallest band index with q = t + #(window band indices
 //      <= q).  If every score is requested, every candidate is evaluated.
-// The LDS footprint (spectrum + 9 KB) allows six workgroups per CU.  Arrays
-// indexed by bin carry one padding slot per 16 bins and histograms one per 8
-// buckets, so segment walks and histogram scans are free of bank conflicts.
+// Histograms use 16-bit counters, two per word, so the LDS footprint is the
+// padded spectrum + 5 KB (22 KB at K = 3991): seven workgroups per CU.
+// Arrays indexed by bin carry one padding slot per 16 bins and histograms one
+// per 8 words, so segment walks and histogram scans are free of bank
+// conflicts.
 // ---------------------------------------------------------------------------
 constexpr int kFT = 256;           // threads per pixel
 constexpr int kFastItems = 16;     // bins per thread: K <= 4096
@@ -383,7 +385,11 @@ __device__ __forceinline__ void seg_dispatch(int nmine, F&& f) {
     if (nmine == kFastItems) f(std::true_type{});
     else f(std::false_type{});
 }
-#define DDHF_IN_SEG(full, j) (decltype(full)::value || (j) < nmine)
+// bin j of the segment is inside [0, K): always when the segment is full
+template <class Full>
+__device__ __forceinline__ bool in_seg(Full, int j, int nmine) {
+    return Full::value || j < nmine;
+}
 
 // Histograms hold 16-bit counters, two per word (a count never exceeds
 // K <= 4096), in 1024 words padded by one per 8 (pad8):
@@ -515,10 +521,10 @@ __global__ __launch_bounds__(kFT) void k_comb_fast(const float* __restrict__ pow
     float fsum = 0.0f;  // 16 terms per thread; the block sum is in FP64
     seg_dispatch(nmine, [&](auto full) {
 #pragma unroll
-        for (int j = 0; j < kFastItems; ++j) v[j] = DDHF_IN_SEG(full, j) ? sP[s0 + j] : 0.0f;
+        for (int j = 0; j < kFastItems; ++j) v[j] = in_seg(full, j, nmine) ? sP[s0 + j] : 0.0f;
 #pragma unroll
         for (int j = 0; j < kFastItems; ++j) {
-            if (DDHF_IN_SEG(full, j)) {
+            if (in_seg(full, j, nmine)) {
                 fsum += v[j];
                 const uint32_t b = __float_as_uint(v[j]);
                 atomicAdd(&sX[pad8((int)((b >> 20) & 0x3FFu))], 1u << ((b >> 26) & 16u));
@@ -540,10 +546,10 @@ __global__ __launch_bounds__(kFT) void k_comb_fast(const float* __restrict__ pow
     seg_dispatch(nmine, [&](auto full) {
 #pragma unroll
         for (int j = 0; j < kFastItems; ++j)
-            lg[j] = DDHF_IN_SEG(full, j) ? __log2f(v[j] > floor_v ? v[j] : floor_v) : 0.0f;
+            lg[j] = in_seg(full, j, nmine) ? __log2f(v[j] > floor_v ? v[j] : floor_v) : 0.0f;
 #pragma unroll
         for (int j = 0; j < kFastItems; ++j) {
-            if (DDHF_IN_SEG(full, j)) {
+            if (in_seg(full, j, nmine)) {
                 const uint32_t b = __float_as_uint(v[j]);
                 const uint32_t d1 = (b >> 20) & 0x7FFu;
                 const int d2 = pad8((int)((b >> 10) & 0x3FFu));
@@ -580,7 +586,7 @@ __global__ __launch_bounds__(kFT) void k_comb_fast(const float* __restrict__ pow
     seg_dispatch(nmine, [&](auto full) {
 #pragma unroll
         for (int j = 0; j < kFastItems; ++j) {
-            if (DDHF_IN_SEG(full, j)) {
+            if (in_seg(full, j, nmine)) {
                 const uint32_t kk = (__float_as_uint(v[j]) >> 10) & 0x1FFFFFu;
                 const uint8_t code =
                     kk < key_lo ? kCodeBelow : (kk > key_hi ? kCodeAbove : kCodeCand);
@@ -690,7 +696,7 @@ __global__ __launch_bounds__(kFT) void k_comb_fast(const float* __restrict__ pow
         seg_dispatch(nmine, [&](auto full) {
 #pragma unroll
             for (int j = 0; j < kFastItems; ++j)
-                if (DDHF_IN_SEG(full, j)) sP[s0 + j] = wm[j];
+                if (in_seg(full, j, nmine)) sP[s0 + j] = wm[j];
         });
     }
     __syncthreads();
