@@ -178,7 +178,7 @@ __device__ __forceinline__ bool next_unit(const WorkDev& wk, const int32_t* row_
     } else {
         int32_t v = 0;
         if (threadIdx.x == 0) v = atomicAdd(wk.counter, 1);
-        id = __shfl(v, 0, 64);
+        id = __builtin_amdgcn_readfirstlane(__shfl(v, 0, 64));
     }
     ++iter;
     if (id >= *wk.n_units) return false;
@@ -370,8 +370,13 @@ __global__ __launch_bounds__(64, 2) void k_ndft_mfma(const int32_t* __restrict__
             }
             __syncthreads();
         }
-        const int col = lane & 31;
-        const int half = lane >> 5;
+        // the lane is passed through an opaque move so that the store offsets are
+        // formed here, per unit, rather than hoisted out of the unit loop and
+        // held in registers across it
+        int lane_u;
+        asm volatile("v_mov_b32 %0, %1" : "=v"(lane_u) : "v"(lane));
+        const int col = lane_u & 31;
+        const int half = lane_u >> 5;
         if (un.slot < 0) {
             float* out = power + (int64_t)un.u * g.K;
 #pragma unroll
