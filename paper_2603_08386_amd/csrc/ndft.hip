@@ -152,14 +152,20 @@ struct WorkDev {
     const int32_t* n_dev;    // plain form: device count of active pixels (nullable)
 };
 
+// Units per wavefront in the plain form, so a wavefront loads the next unit's
+// events while it computes the current one.  Wavefront w takes units w,
+// w + G, ... (G = grid size): with the list in decreasing cost, each heavy
+// unit is paired with a light one.
+constexpr int kPlainUnits = 2;
+
 // Finds the next unit of this wavefront.  Returns false when there is none.
 template <int MODE>
 __device__ __forceinline__ bool next_unit(const WorkDev& wk, const int32_t* row_ptr,
                                           const int32_t* active, int32_t n_active, int n_wtiles,
                                           int64_t& iter, Unit& un) {
     if (MODE == kModePlain) {
-        if (iter > 0) return false;
-        const int64_t unit = (int64_t)blockIdx.x;
+        if (iter >= kPlainUnits) return false;
+        const int64_t unit = (int64_t)blockIdx.x + iter * (int64_t)gridDim.x;
         un.u = (int32_t)(unit / n_wtiles);
         un.wt = (int)(unit % n_wtiles);
         const int32_t na = wk.n_dev ? *wk.n_dev : n_active;
@@ -191,15 +197,24 @@ struct EvStage {
     float a, wc, ws, pad;
 };
 
-// Stages events [c0, c0 + 64) of a unit: exact residues A = f_tile t mod Q and
-// D = df t mod Q as fixed-point fractions, and the step phasor
-// exp(i 2 pi step_mul D / Q) from the 48-bit fraction of D.
-__device__ __forceinline__ void stage_event(EvStage* st, int lane, int32_t c0, int32_t end,
-                                            const uint32_t* t_rel, const float* av,
-                                            uint64_t f_tile, const GridDev& g, uint32_t step_mul) {
+// Loads this lane's event of the chunk [c0, c0 + 64) (time, weight).
+__device__ __forceinline__ void load_event(int lane, int32_t c0, int32_t end,
+                                           const uint32_t* t_rel, const float* av, uint32_t& t,
+                                           float& a) {
+    const int32_t e = c0 + lane;
+    t = e < end ? t_rel[e] : 0u;
+    a = e < end ? av[e] : 0.0f;
+}
+
+// Stages events [c0, c0 + 64) of a unit from the lanes' loaded (t, a): exact
+// residues A = f_tile t mod Q and D = df t mod Q as fixed-point fractions,
+// and the step phasor exp(i 2 pi step_mul D / Q) from the 48-bit fraction of D.
+__device__ __forceinline__ void stage_loaded(EvStage* st, int lane, int32_t c0, int32_t end,
+                                             uint32_t t_lane, float a_lane, uint64_t f_tile,
+                                             const GridDev& g, uint32_t step_mul) {
     const int32_t e = c0 + lane;
     if (e < end) {
-        const uint64_t t = t_rel[e];
+        const uint64_t t = t_lane;
         EvStage s;
         const uint32_t A = mod_q(f_tile * t, g);
         const uint32_t D = mod_q((uint64_t)g.df * t, g);
@@ -211,9 +226,18 @@ __device__ __forceinline__ void stage_event(EvStage* st, int lane, int32_t c0, i
         s.pad = 0.0f;
         // step phasor exp(2 pi i step_mul D / Q) from the 48-bit fraction
         sincos_fixed((uint32_t)((f.F * step_mul) >> 16), s.ws, s.wc);
-        s.a = av[e];
+        s.a = a_lane;
         st[lane] = s;
     }
+}
+
+__device__ __forceinline__ void stage_event(EvStage* st, int lane, int32_t c0, int32_t end,
+                                            const uint32_t* t_rel, const float* av,
+                                            uint64_t f_tile, const GridDev& g, uint32_t step_mul) {
+    uint32_t t;
+    float a;
+    load_event(lane, c0, end, t_rel, av, t, a);
+    stage_loaded(st, lane, c0, end, t, a, f_tile, g, step_mul);
 }
 
 template <int BPL, int MODE>
@@ -330,7 +354,15 @@ __global__ __launch_bounds__(64, 2) void k_ndft_mfma(const int32_t* __restrict__
     const uint32_t mV = (uint32_t)r32;         // V column
     int64_t iter = 0;
     Unit un;
-    while (next_unit<MODE>(wk, row_ptr, active, n_active, n_wtiles, iter, un)) {
+    bool have = next_unit<MODE>(wk, row_ptr, active, n_active, n_wtiles, iter, un);
+    // the lane's event of the chunk to stage next; the following chunk (or the
+    // next unit's first) is loaded before each chunk's MFMA loop
+    uint32_t t_ld = 0u;
+    float a_ld = 0.0f;
+    if (have) load_event(lane, un.beg, un.end, t_rel, av, t_ld, a_ld);
+    while (have) {
+        Unit nx;
+        const bool have_nx = next_unit<MODE>(wk, row_ptr, active, n_active, n_wtiles, iter, nx);
         const int tile_base = un.wt * NB * 1024;
         const uint64_t f_tile = (uint64_t)(g.f0 + (int64_t)tile_base * g.df);
         f32x16 cre[NB], cim[NB];
@@ -339,9 +371,12 @@ __global__ __launch_bounds__(64, 2) void k_ndft_mfma(const int32_t* __restrict__
 #pragma unroll
             for (int r = 0; r < 16; ++r) { cre[b][r] = 0.0f; cim[b][r] = 0.0f; }
         }
+        if (un.beg >= un.end && have_nx) load_event(lane, nx.beg, nx.end, t_rel, av, t_ld, a_ld);
         for (int32_t c0 = un.beg; c0 < un.end; c0 += 64) {
-            stage_event(st, lane, c0, un.end, t_rel, av, f_tile, g, 2048u);
+            stage_loaded(st, lane, c0, un.end, t_ld, a_ld, f_tile, g, 2048u);
             __syncthreads();
+            if (c0 + 64 < un.end) load_event(lane, c0 + 64, un.end, t_rel, av, t_ld, a_ld);
+            else if (have_nx) load_event(lane, nx.beg, nx.end, t_rel, av, t_ld, a_ld);
             const int ne = (un.end - c0) < 64 ? (un.end - c0) : 64;
             // software pipelined: the next event's phasors are formed while this
             // event's MFMAs run (no branch inside the body, so they interleave)
@@ -399,6 +434,8 @@ __global__ __launch_bounds__(64, 2) void k_ndft_mfma(const int32_t* __restrict__
                 }
             }
         }
+        un = nx;
+        have = have_nx;
     }
 }
 
@@ -570,7 +607,8 @@ static int run_plan(const Plan& p, const PlanWs& w, KernelPlain kp, KernelList k
     if (p.mode == kModePlain) {
         const int64_t units = (int64_t)n_active * p.n_wtiles;
         if (units > 0x7FFFFFFFLL) return DDHF_EINVAL;
-        hipLaunchKernelGGL(kp, dim3((unsigned)units), dim3(64), 0, s, row_ptr, t_rel, a, active,
+        const int64_t waves = (units + kPlainUnits - 1) / kPlainUnits;
+        hipLaunchKernelGGL(kp, dim3((unsigned)waves), dim3(64), 0, s, row_ptr, t_rel, a, active,
                            n_active, g, p.n_wtiles, power, wk);
         DDHF_LAUNCH_CHECK();
         return DDHF_OK;
