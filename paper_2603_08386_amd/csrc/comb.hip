@@ -549,12 +549,13 @@ __global__ __launch_bounds__(kFT) void k_comb_fast(const float* __restrict__ pow
             lg[j] = in_seg(full, j, nmine) ? __log2f(v[j] > floor_v ? v[j] : floor_v) : 0.0f;
 #pragma unroll
         for (int j = 0; j < kFastItems; ++j) {
-            if (in_seg(full, j, nmine)) {
-                const uint32_t b = __float_as_uint(v[j]);
-                const uint32_t d1 = (b >> 20) & 0x7FFu;
+            const uint32_t b = __float_as_uint(v[j]);
+            const uint32_t d1 = (b >> 20) & 0x7FFu;
+            // one range test: few bins fall in [d1lo, d1hi]
+            if (in_seg(full, j, nmine) && d1 - d1lo <= d1hi - d1lo) {
                 const int d2 = pad8((int)((b >> 10) & 0x3FFu));
-                if (d1 == d1lo) atomicAdd(&sX[d2], 1u);
-                if (d1 == d1hi) atomicAdd(&sX[d2], 1u << 16);
+                const uint32_t inc = (d1 == d1lo ? 1u : 0u) + (d1 == d1hi ? 1u << 16 : 0u);
+                if (inc) atomicAdd(&sX[d2], inc);
             }
         }
     });
