@@ -449,6 +449,40 @@ def test_ndft_large_sampled(form):
     assert err <= TOL_P
 
 
+def test_bench_launch_large_sampled():
+    """The launch bench.py times (MFMA, 4096 bins per wavefront, plain,
+    cost-ordered) on the 1280x720 window it times: sampled rows of the power
+    against the oracle, and the comb of those rows against the oracle's comb on
+    the same FP32 spectra."""
+    win = synth.large_window()
+    banner(f"bench launch large n={win.n}")
+    g, P, act = gpu_power_form(win, 1, 64, 0, 0, True)
+    g.score()
+    torch.cuda.synchronize()
+    na = g.n_active
+    sf, snr, b = to_np(g.sf, na), to_np(g.snr, na), to_np(g.bin, na)
+    r = oracle_window(win)
+    order = np.argsort(act, kind="stable")
+    assert np.array_equal(act[order], r["active"])
+    rp = r["row_ptr"]
+    counts = rp[r["active"] + 1] - rp[r["active"]]
+    rows = stratified_sample(counts, 40, np.random.default_rng(2))
+    P64 = oracle.ndft_power(rp, r["t_rel"], r["a"], r["active"][rows], win.grid)
+    err = power_err(P[order][rows], P64, rp, r["active"][rows], r["a"])
+    banner(f"  sampled rows {rows.size} max err {err:.3e}")
+    assert err <= TOL_P
+    prm = win.params
+    for q in order[rows]:
+        row = P[q].astype(np.float64)
+        sf64 = oracle.spectral_flatness(row, prm.eps_rel)
+        s64, b64, all64 = oracle.comb_score(row, win.grid, prm, want_all=True)
+        assert sf[q] == pytest.approx(sf64, rel=2e-5, abs=1e-7), q
+        assert snr[q] == pytest.approx(s64, rel=2e-5, abs=1e-7), q
+        top = np.sort(all64)[::-1]
+        if top.size < 2 or top[0] > (1 + 1e-3) * top[1]:
+            assert b[q] == b64, q
+
+
 # ---------------------------------------------------------------------------
 # 7. autotuner
 # ---------------------------------------------------------------------------
