@@ -481,6 +481,11 @@ def test_bench_launch_large_sampled():
         top = np.sort(all64)[::-1]
         if top.size < 2 or top[0] > (1 + 1e-3) * top[1]:
             assert b[q] == b64, q
+    # detection at full size on these scores: mask, labels and boxes exact
+    banner("  detect 1280x720 on the GPU's scores")
+    n = detect_compare(act, rp, sf.astype(np.float64), snr.astype(np.float64), b, win.W, win.H,
+                       win.grid, prm)
+    assert n >= 1
 
 
 # ---------------------------------------------------------------------------
