@@ -584,21 +584,33 @@ __global__ __launch_bounds__(kFT) void k_comb_fast(const float* __restrict__ pow
     const uint32_t key_hi = (d1hi << 10) | (uint32_t)l2hi.d;
     const uint32_t below_base = l2lo.before;  // values with a 21-bit key below key_lo
     // ---- classify: below / above / candidate (histograms are dead now) ------
-    seg_dispatch(nmine, [&](auto full) {
+    {
+        // candidates of the segment as a bit mask; one list append per wavefront
+        uint32_t cmask = 0u;
+        seg_dispatch(nmine, [&](auto full) {
 #pragma unroll
-        for (int j = 0; j < kFastItems; ++j) {
-            if (in_seg(full, j, nmine)) {
-                const uint32_t kk = (__float_as_uint(v[j]) >> 10) & 0x1FFFFFu;
-                const uint8_t code =
-                    kk < key_lo ? kCodeBelow : (kk > key_hi ? kCodeAbove : kCodeCand);
-                if (code == kCodeCand) {
-                    const uint32_t pos = atomicAdd(&s_nlist, 1u);
-                    if (pos < kListCap) sList[pos] = (uint16_t)(k0 + j);
+            for (int j = 0; j < kFastItems; ++j) {
+                if (in_seg(full, j, nmine)) {
+                    const uint32_t kk = (__float_as_uint(v[j]) >> 10) & 0x1FFFFFu;
+                    const uint8_t code =
+                        kk < key_lo ? kCodeBelow : (kk > key_hi ? kCodeAbove : kCodeCand);
+                    cmask |= (code == kCodeCand ? 1u : 0u) << j;
+                    sCode[s0 + j] = code;
                 }
-                sCode[s0 + j] = code;
             }
+        });
+        const uint32_t cnt = (uint32_t)__popc(cmask);
+        const uint32_t incl = wave_incl_scan(cnt);
+        uint32_t base = 0u;
+        if (__lane_id() == kWave - 1 && incl) base = atomicAdd(&s_nlist, incl);
+        uint32_t pos = (uint32_t)__builtin_amdgcn_readlane((int)base, kWave - 1) + incl - cnt;
+        while (cmask) {
+            const int j = __ffs(cmask) - 1;
+            cmask &= cmask - 1u;
+            if (pos < kListCap) sList[pos] = (uint16_t)(k0 + j);
+            ++pos;
         }
-    });
+    }
     __syncthreads();
     // ---- exact ranks of the candidates by (value, bin) ----------------------
     const int nL = (int)s_nlist;
