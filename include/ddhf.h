@@ -104,8 +104,9 @@ typedef struct {
     int64_t time_unsorted; /* number of i >= 1 with t[i] < t[i-1] */
 } ddhf_counters_t;
 
-/* NDFT launch shape.  NULL selects the plain launch: one wavefront per
- * (active pixel, bin tile), lanes owning bins, events staged in LDS.
+/* NDFT launch shape.  NULL selects the plain launch: each wavefront takes
+ * two (active pixel, bin tile) units of the list, w and w + grid size, lanes
+ * owning bins, events staged in LDS.
  *   kernel:        0 = VALU (lanes own bins, phasor recurrence per lane),
  *                  1 = MFMA (factorised: F[J b + s] = sum_e U[b,e] V[e,s]
  *                      as FP32 matrix-core products, J = 32);
