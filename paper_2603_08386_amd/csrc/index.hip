@@ -309,6 +309,9 @@ constexpr int kPrepItems = 8;
 
 // Window filter and sort keys.  Each thread handles kPrepItems events; the
 // five event counters are reduced per workgroup and added with one atomic each.
+// VEC: the thread's events are consecutive and moved with 16-byte loads and
+// stores (all arrays 16-byte aligned, checked on the host); otherwise strided.
+template <bool VEC>
 __global__ __launch_bounds__(kPrepThreads) void k_prepare(
     const uint16_t* __restrict__ x, const uint16_t* __restrict__ y, const int8_t* __restrict__ p,
     const int64_t* __restrict__ t, int64_t n, int32_t W, int32_t H, int64_t t0, int64_t T_w,
@@ -317,24 +320,73 @@ __global__ __launch_bounds__(kPrepThreads) void k_prepare(
     __shared__ uint32_t red[5][kPrepThreads / kWave];
     uint32_t c[5] = {0, 0, 0, 0, 0};  // kept, window, sensor, polarity, unsorted
     const uint32_t npix = (uint32_t)W * (uint32_t)H;
-    const int64_t base = (int64_t)blockIdx.x * kPrepThreads * kPrepItems + threadIdx.x;
+    // one event: category, pixel key, relative time and time | sign word
+    auto one = [&](int64_t ti, uint32_t xi, uint32_t yi, int8_t pi, uint32_t& kp, uint32_t& tr,
+                   uint32_t& tpv) {
+        const bool win = ti >= t0 && ti < t0 + T_w;
+        const bool sen = xi < (uint32_t)W && yi < (uint32_t)H;
+        const bool pol = pi >= -1 && pi <= 1;
+        const int cat = !win ? 1 : (!sen ? 2 : (!pol ? 3 : 0));
+        c[cat] += 1u;
+        kp = cat == 0 ? yi * (uint32_t)W + xi : npix;
+        tr = cat == 0 ? (uint32_t)(ti - t0) : 0u;
+        tpv = tr | (pi > 0 ? 0u : 0x80000000u);  // t_rel < 2^31: sign in the top bit
+    };
+    auto scalar = [&](int64_t i) {
+        const int64_t ti = t[i];
+        uint32_t kp, tr, tpv;
+        one(ti, x[i], y[i], p[i], kp, tr, tpv);
+        key_pix[i] = kp;
+        if (key_t) key_t[i] = tr;
+        vals[i] = (uint32_t)i;
+        tp[i] = tpv;
+        if (i > 0 && ti < t[i - 1]) c[4] += 1u;
+    };
+    if (VEC) {
+        const int64_t i0 = ((int64_t)blockIdx.x * kPrepThreads + threadIdx.x) * kPrepItems;
+        if (i0 + kPrepItems <= n) {
+            const uint4 xv = *(const uint4*)(x + i0);  // 8 x u16
+            const uint4 yv = *(const uint4*)(y + i0);
+            const uint2 pv = *(const uint2*)(p + i0);  // 8 x i8
+            int64_t tv[kPrepItems];
 #pragma unroll
-    for (int it = 0; it < kPrepItems; ++it) {
-        const int64_t i = base + (int64_t)it * kPrepThreads;
-        if (i < n) {
-            const int64_t ti = t[i];
-            const bool win = ti >= t0 && ti < t0 + T_w;
-            const bool sen = x[i] < W && y[i] < H;
-            const int8_t pi = p[i];
-            const bool pol = pi >= -1 && pi <= 1;
-            const int cat = !win ? 1 : (!sen ? 2 : (!pol ? 3 : 0));
-            c[cat] += 1u;
-            key_pix[i] = cat == 0 ? (uint32_t)y[i] * (uint32_t)W + x[i] : npix;
-            const uint32_t tr = cat == 0 ? (uint32_t)(ti - t0) : 0u;
-            if (key_t) key_t[i] = tr;
-            vals[i] = (uint32_t)i;
-            tp[i] = tr | (pi > 0 ? 0u : 0x80000000u);  // t_rel < 2^31: sign in the top bit
-            if (i > 0 && ti < t[i - 1]) c[4] += 1u;
+            for (int q = 0; q < kPrepItems / 2; ++q) {
+                const longlong2 tt = *(const longlong2*)(t + i0 + 2 * q);
+                tv[2 * q] = tt.x;
+                tv[2 * q + 1] = tt.y;
+            }
+            const int64_t tprev = i0 > 0 ? t[i0 - 1] : tv[0];
+            const uint32_t xw[4] = {xv.x, xv.y, xv.z, xv.w}, yw[4] = {yv.x, yv.y, yv.z, yv.w};
+            const uint32_t pw[2] = {pv.x, pv.y};
+            uint32_t kp[kPrepItems], tr[kPrepItems], tpv[kPrepItems];
+#pragma unroll
+            for (int q = 0; q < kPrepItems; ++q) {
+                const uint32_t xi = (xw[q >> 1] >> (16 * (q & 1))) & 0xFFFFu;
+                const uint32_t yi = (yw[q >> 1] >> (16 * (q & 1))) & 0xFFFFu;
+                const int8_t pi = (int8_t)(pw[q >> 2] >> (8 * (q & 3)));
+                one(tv[q], xi, yi, pi, kp[q], tr[q], tpv[q]);
+                if (tv[q] < (q ? tv[q - 1] : tprev)) c[4] += 1u;
+            }
+            const uint32_t b = (uint32_t)i0;
+            *(uint4*)(key_pix + i0) = make_uint4(kp[0], kp[1], kp[2], kp[3]);
+            *(uint4*)(key_pix + i0 + 4) = make_uint4(kp[4], kp[5], kp[6], kp[7]);
+            if (key_t) {
+                *(uint4*)(key_t + i0) = make_uint4(tr[0], tr[1], tr[2], tr[3]);
+                *(uint4*)(key_t + i0 + 4) = make_uint4(tr[4], tr[5], tr[6], tr[7]);
+            }
+            *(uint4*)(vals + i0) = make_uint4(b, b + 1, b + 2, b + 3);
+            *(uint4*)(vals + i0 + 4) = make_uint4(b + 4, b + 5, b + 6, b + 7);
+            *(uint4*)(tp + i0) = make_uint4(tpv[0], tpv[1], tpv[2], tpv[3]);
+            *(uint4*)(tp + i0 + 4) = make_uint4(tpv[4], tpv[5], tpv[6], tpv[7]);
+        } else {
+            for (int64_t i = i0; i < n; ++i) scalar(i);
+        }
+    } else {
+        const int64_t base = (int64_t)blockIdx.x * kPrepThreads * kPrepItems + threadIdx.x;
+#pragma unroll
+        for (int it = 0; it < kPrepItems; ++it) {
+            const int64_t i = base + (int64_t)it * kPrepThreads;
+            if (i < n) scalar(i);
         }
     }
     if (!counters) return;
@@ -459,9 +511,17 @@ extern "C" int ddhf_build_pixel_index(const uint16_t* x, const uint16_t* y, cons
         DDHF_LAUNCH_CHECK();
     }
     if (n > 0) {
-        hipLaunchKernelGGL(k_prepare, dim3(blocks_for(n, kPrepThreads * kPrepItems)),
-                           dim3(kPrepThreads), 0, s, x, y, p, t_us, n,
-                           W, H, t0_us, T_w_us, key_pix, key_t, vals, tp0, counters);
+        auto a16 = [](const void* q) { return ((uintptr_t)q & 15u) == 0; };
+        const bool vec = a16(x) && a16(y) && ((uintptr_t)p & 7u) == 0 && a16(t_us) &&
+                         a16(key_pix) && (!key_t || a16(key_t)) && a16(vals) && a16(tp0);
+        if (vec)
+            hipLaunchKernelGGL(k_prepare<true>, dim3(blocks_for(n, kPrepThreads * kPrepItems)),
+                               dim3(kPrepThreads), 0, s, x, y, p, t_us, n, W, H, t0_us, T_w_us,
+                               key_pix, key_t, vals, tp0, counters);
+        else
+            hipLaunchKernelGGL(k_prepare<false>, dim3(blocks_for(n, kPrepThreads * kPrepItems)),
+                               dim3(kPrepThreads), 0, s, x, y, p, t_us, n, W, H, t0_us, T_w_us,
+                               key_pix, key_t, vals, tp0, counters);
         DDHF_LAUNCH_CHECK();
     }
     uint32_t* keys = key_pix;
