@@ -98,10 +98,10 @@ int fill_u32(uint32_t* p, uint32_t v, int64_t n, hipStream_t s) {
 // stable LSD radix sort of (u32 key, u32 value) pairs
 // ---------------------------------------------------------------------------
 constexpr int kRadixThreads = 256;
-constexpr int kRadixItems = 16;
-constexpr int kRadixTile = kRadixThreads * kRadixItems;  // 4096
+constexpr int kRadixItems = 8;
+constexpr int kRadixTile = kRadixThreads * kRadixItems;  // 2048
 constexpr int kRadixWaves = kRadixThreads / kWave;       // 4
-constexpr int kWaveSpan = kRadixTile / kRadixWaves;      // 1024 keys per wave
+constexpr int kWaveSpan = kRadixTile / kRadixWaves;      // 512 keys per wave
 
 __device__ __forceinline__ int64_t dev_count(int64_t n_host, const int32_t* n_dev) {
     if (!n_dev) return n_host;
