@@ -38,7 +38,10 @@ enum {
     DDHF_EINVAL = 1,   /* null pointer, size out of range, grid that could overflow */
     DDHF_ENOSPACE = 2, /* workspace smaller than *_workspace_size reported */
     DDHF_EHIP = 3,     /* a HIP launch or runtime call failed */
-    DDHF_ETRUNC = 4    /* reserved: results truncated (reported through counts) */
+    DDHF_ETRUNC = 4    /* results truncated by a size limit; every output is still written
+                          up to that limit and the true counts are reported.  Returned by
+                          calls that synchronise (ddhf_stream_step); the stream-ordered
+                          calls report the same condition through their device counts */
 };
 
 /* Text for a status code (static storage). */
@@ -234,9 +237,13 @@ int ddhf_detect_workspace_size(int32_t W, int32_t H, size_t* bytes);
  * box area w*h >= a_min, merged while two centres are closer than alpha times
  * the largest side of the pair (Eq. 12, repeated to a fixed point), sorted by
  * (y0, x0, y1, x1, n_px, rep_pixel).  n_boxes [2] (device i32): [0] = number
- * of final boxes (may exceed max_boxes: only max_boxes are written),
- * [1] = components dropped because more than DDHF_DETECT_MAX_CANDIDATES
- * passed the area filter. */
+ * of final boxes (may exceed max_boxes: only the first max_boxes are
+ * written), [1] = components left out of the merge because more than
+ * DDHF_DETECT_MAX_CANDIDATES passed the area filter (the merge then takes the
+ * DDHF_DETECT_MAX_CANDIDATES components of smallest label, a deterministic
+ * choice).  Both truncations are device-side counts (this call does not
+ * synchronise, so it never returns DDHF_ETRUNC); mask and labels are always
+ * complete. */
 int ddhf_detect(const int32_t* active, const int32_t* row_ptr, const float* sf,
                 const float* snr_best, const int32_t* bin_best, int32_t n_active, int32_t W,
                 int32_t H, const ddhf_grid_t* grid, const ddhf_params_t* prm, uint8_t* mask,
@@ -286,7 +293,12 @@ int ddhf_soft_comb_backward(const int32_t* row_ptr, const uint32_t* t_rel, const
 typedef struct {
     int32_t W, H;
     int64_t T_w_us;          /* window length (< 2^31 us) */
-    int64_t t_origin_us;     /* stream epoch: earlier events are rejected; stream < 2^32 us */
+    int64_t t_origin_us;     /* initial stream epoch: earlier events are rejected.  Times are
+                                kept as 32-bit offsets from the epoch, which moves forward by
+                                whole grid periods 1e9/gcd(1e9, f0, df) us once a step is 2^31
+                                us past it (phases, and so results, stay bit-identical), so a
+                                stream may run indefinitely; two consecutive steps must be less
+                                than about 2^31 us apart (else ddhf_stream_step: DDHF_EINVAL) */
     int32_t ring_cap;        /* events kept per pixel (power of two, 2..4096); extra = oldest lost */
     int32_t max_step_events; /* events staged between two steps */
     int32_t max_touched;     /* pixels that may change in one step */
@@ -307,7 +319,7 @@ typedef struct {
     int32_t n_active;         /* after the last step */
     int32_t n_touched;
     int32_t n_recomputed;
-    int32_t reserved;
+    int32_t epoch_shifts;     /* times the epoch moved forward (see t_origin_us) */
 } ddhf_stream_stats_t;
 
 /* Allocates the device state (rings, log, scores, scratch) and pinned staging
@@ -321,10 +333,15 @@ int ddhf_stream_destroy(ddhf_stream_t* st);
 int ddhf_stream_push(ddhf_stream_t* st, const uint16_t* x, const uint16_t* y, const int8_t* p,
                      const int64_t* t_us, int32_t n);
 
-/* Runs one step with window end t_now_us (>= the last staged time) on the
- * stream's own HIP stream (graph-launched if use_graph != 0), waits for it, and
- * copies up to max_boxes boxes to boxes_host; *n_boxes_host = number of boxes.
- * DDHF_ENOSPACE if the window would hold more events than the device log. */
+/* Runs one step with window end t_now_us (>= the last staged time and >= the
+ * previous step's t_now_us) on the stream's own HIP stream (graph-launched if
+ * use_graph != 0), waits for it, and copies up to max_boxes boxes to
+ * boxes_host; *n_boxes_host = number of boxes.  DDHF_ENOSPACE if the window
+ * would hold more events than the device log; DDHF_EINVAL for a window end
+ * that goes back in time or lies 2^32 us or more past the epoch; DDHF_ETRUNC
+ * (after writing every output) when the frame had more boxes than max_boxes
+ * or than the stream's max_boxes, or detect left components out of the merge
+ * (see ddhf_detect). */
 int ddhf_stream_step(ddhf_stream_t* st, int64_t t_now_us, int32_t use_graph,
                      ddhf_box_t* boxes_host, int32_t max_boxes, int32_t* n_boxes_host);
 

@@ -282,17 +282,15 @@ __global__ __launch_bounds__(256) void k_det_accum(int32_t W, int32_t H,
     }
 }
 
-__global__ void k_det_collect(int32_t npix, const uint8_t* __restrict__ mask,
-                              const int32_t* __restrict__ labels, int32_t a_min, DetectWs d) {
-    const int32_t q = blockIdx.x * blockDim.x + threadIdx.x;
-    if (q >= npix || !mask[q] || labels[q] != q) return;
+__device__ __forceinline__ bool passes_area(int32_t npix, const uint8_t* __restrict__ mask,
+                                            const int32_t* __restrict__ labels, int32_t a_min,
+                                            const DetectWs& d, int32_t q) {
+    if (q >= npix || !mask[q] || labels[q] != q) return false;
     const int64_t area = (int64_t)(d.x1[q] - d.x0[q] + 1) * (int64_t)(d.y1[q] - d.y0[q] + 1);
-    if (area < a_min) return;
-    const int32_t slot = atomicAdd(&d.ctr[0], 1);
-    if (slot >= kCap) {
-        atomicAdd(&d.ctr[1], 1);
-        return;
-    }
+    return area >= a_min;
+}
+
+__device__ __forceinline__ void write_candidate(const DetectWs& d, int32_t q, int32_t slot) {
     ddhf_box_t b;
     b.x0 = d.x0[q];
     b.y0 = d.y0[q];
@@ -304,6 +302,50 @@ __global__ void k_det_collect(int32_t npix, const uint8_t* __restrict__ mask,
     b.rep_snr = __uint_as_float((uint32_t)(key >> 32));
     b.f_dom_hz = __int_as_float(q);  // carries the root pixel (bit pattern) until the merge
     d.cand[slot] = b;
+}
+
+// Components that pass the area filter become merge candidates in slots taken
+// by an atomic counter (their order does not matter: the merge sorts them).
+__global__ void k_det_collect(int32_t npix, const uint8_t* __restrict__ mask,
+                              const int32_t* __restrict__ labels, int32_t a_min, DetectWs d) {
+    const int32_t q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (!passes_area(npix, mask, labels, a_min, d, q)) return;
+    const int32_t slot = atomicAdd(&d.ctr[0], 1);
+    if (slot >= kCap) {
+        atomicAdd(&d.ctr[1], 1);
+        return;
+    }
+    write_candidate(d, q, slot);
+}
+
+// More components than candidate slots: which ones the atomic counter kept is
+// arbitrary, so one workgroup refills the slots with the kCap components of
+// smallest root pixel (a deterministic choice; ctr[1] counts the rest).
+// Exits at once when everything fitted.
+__global__ __launch_bounds__(1024) void k_det_collect_capped(int32_t npix,
+                                                            const uint8_t* __restrict__ mask,
+                                                            const int32_t* __restrict__ labels,
+                                                            int32_t a_min, DetectWs d) {
+    __shared__ int32_t wsum[1024 / kWave];
+    if (d.ctr[0] <= kCap) return;  // uniform
+    const int tid = threadIdx.x, w = tid / kWave;
+    int32_t base = 0;
+    for (int32_t c0 = 0; c0 < npix && base < kCap; c0 += 1024) {
+        const int32_t q = c0 + tid;
+        const bool pass = passes_area(npix, mask, labels, a_min, d, q);
+        const uint64_t bal = __builtin_amdgcn_ballot_w64(pass);
+        if (__lane_id() == 0) wsum[w] = __popcll(bal);
+        __syncthreads();
+        int32_t before = base + (int32_t)__popcll(bal & lanemask_lt());
+        int32_t total = 0;
+        for (int k = 0; k < 1024 / kWave; ++k) {
+            before += k < w ? wsum[k] : 0;
+            total += wsum[k];
+        }
+        if (pass && before < kCap) write_candidate(d, q, before);
+        base += total;
+        __syncthreads();
+    }
 }
 
 // ---- single-workgroup merge ----------------------------------------------
@@ -572,6 +614,9 @@ int detect_run(const int32_t* active, const int32_t* row_ptr, const float* sf,
         DDHF_LAUNCH_CHECK();
         hipLaunchKernelGGL(k_det_collect, gp, dim3(256), 0, s, (int32_t)npix, mask, labels,
                            prm->a_min, d);
+        DDHF_LAUNCH_CHECK();
+        hipLaunchKernelGGL(k_det_collect_capped, dim3(1), dim3(1024), 0, s, (int32_t)npix, mask,
+                           labels, prm->a_min, d);
         DDHF_LAUNCH_CHECK();
     }
     hipLaunchKernelGGL(k_det_merge, dim3(1), dim3(kMergeThreads), merge_lds_bytes(), s, d,

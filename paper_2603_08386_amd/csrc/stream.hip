@@ -17,9 +17,14 @@
 // in a hipGraph and replayed.  Staged events are read straight from pinned host
 // memory; results are written to pinned host memory by a kernel.
 //
-// Phases use t - t_origin (the stream epoch) as the time reference; the power
-// of a window does not depend on the reference, so scores agree with a plain
-// recompute of the same window within FP32 rounding.
+// Times are stored as 32-bit offsets from a stream epoch held in device
+// memory.  Before the offsets could overflow, the host moves the epoch forward
+// by a whole number of grid periods T_per = 1e9 / gcd(1e9, f0, df) us and
+// subtracts that shift from every stored time: for every grid frequency f the
+// residue (f t) mod 1e9 is unchanged, so each phase of Eq. 6 stays exactly the
+// same and a stream can run indefinitely.  The power of a window does not
+// depend on the time reference, so scores agree with a plain recompute of the
+// same window within FP32 rounding.
 #include "ddhf_internal.h"
 
 #include <new>
@@ -36,7 +41,8 @@ struct StageHdr {
 struct StreamDev {
     // geometry / parameters
     int32_t W, H, npix, R, K, n_min;
-    int64_t T_w, origin;
+    int64_t T_w;
+    int64_t* epoch;              // [0] stream epoch (us): stored times are t - epoch
     uint32_t log_mask;
     // state
     uint32_t *ring_t, *head, *count, *stamp, *nstamp, *nbeg, *nend;
@@ -53,7 +59,7 @@ struct StreamDev {
     const int8_t* hp;
     const int64_t* ht;
     uint32_t *keys, *vals, *keys2, *vals2;
-    uint32_t* stg_t;   // t - origin of staged events
+    uint32_t* stg_t;   // t - epoch of staged events
     float* stg_a;
     int32_t* n_stage;  // device copy of the staged count
     uint32_t* exp_end_lo;  // low word of the new log head
@@ -93,26 +99,35 @@ __global__ void k_st_accept(StreamDev d, int32_t max_stage) {
     const int32_t n = *d.n_stage < max_stage ? *d.n_stage : max_stage;
     if (i >= n) return;
     const int64_t t_now = d.hdr->t_now;
+    const int64_t org = *d.epoch;
     const int64_t t = d.ht[i];
     const uint16_t x = d.hx[i], y = d.hy[i];
     const int8_t p = d.hp[i];
-    const bool ok = t >= t_now - d.T_w && t < t_now && t >= d.origin && x < d.W && y < d.H &&
+    const bool ok = t >= t_now - d.T_w && t < t_now && t >= org && x < d.W && y < d.H &&
                     p >= -1 && p <= 1;
     const uint32_t pix = ok ? (uint32_t)y * (uint32_t)d.W + x : (uint32_t)d.npix;
     d.keys[i] = pix;
     d.vals[i] = (uint32_t)i;
-    d.stg_t[i] = (uint32_t)(t - d.origin);
+    d.stg_t[i] = (uint32_t)(t - org);  // read only for accepted events (t - org < 2^32)
     d.stg_a[i] = p > 0 ? 1.0f : -1.0f;
+    // The log stays time ordered for the expiry search: a rejected event's time
+    // is clamped into [window start, window end] (an accepted one is inside).
+    // Pushes are time ordered and window ends never decrease, so the clamped
+    // times never decrease either.
+    int64_t lt = t - org;
+    const int64_t lo_c = t_now - d.T_w - org > 0 ? t_now - d.T_w - org : 0;
+    const int64_t hi_c = t_now - org;
+    lt = lt < lo_c ? lo_c : (lt > hi_c ? hi_c : lt);
     const unsigned long long tail = d.log_ht[1];
     d.log_pix[(tail + i) & d.log_mask] = pix;
-    d.log_t[(tail + i) & d.log_mask] = (uint32_t)(t - d.origin);
+    d.log_t[(tail + i) & d.log_mask] = (uint32_t)lt;
     if (!ok) atomicAdd(&d.stats[2], 1ull);
 }
 
 // first log entry at or after the window start (log is time ordered)
 __global__ void k_st_expire_find(StreamDev d) {
     if (threadIdx.x != 0 || blockIdx.x != 0) return;
-    const int64_t lo_t = d.hdr->t_now - d.T_w - d.origin;
+    const int64_t lo_t = d.hdr->t_now - d.T_w - *d.epoch;
     unsigned long long lo = d.log_ht[0], hi = d.log_ht[1];  // entries before this step's appends
     while (lo < hi) {
         const unsigned long long mid = lo + (hi - lo) / 2;
@@ -172,7 +187,7 @@ __global__ void k_st_update(StreamDev d, const uint32_t* __restrict__ vals) {
     }
     const uint32_t p = d.touched[idx];
     const uint32_t step = d.step[0];
-    const int64_t lo_t = d.hdr->t_now - d.T_w - d.origin;
+    const int64_t lo_t = d.hdr->t_now - d.T_w - *d.epoch;
     uint32_t h = d.head[p], c = d.count[p];
     const uint32_t R = (uint32_t)d.R;
     uint32_t* rt = d.ring_t + (int64_t)p * R;
@@ -270,6 +285,7 @@ __global__ void k_st_finish(StreamDev d, ddhf_box_t* __restrict__ out_host,
         nb_host[1] = *d.n_act;
         nb_host[2] = *d.n_touched;
         nb_host[3] = *d.n_tact;
+        nb_host[4] = nb[1];  // merge candidates dropped (more than the detect cap)
         const int32_t ns = *d.n_stage < max_stage ? *d.n_stage : max_stage;
         d.log_ht[0] = *d.exp_end;
         d.log_ht[1] += (unsigned long long)ns;
@@ -277,6 +293,32 @@ __global__ void k_st_finish(StreamDev d, ddhf_box_t* __restrict__ out_host,
         d.stats[1] += (unsigned long long)ns;
         __threadfence_system();
     }
+}
+
+// Moves the epoch forward by `shift` us (a multiple of the grid period):
+// every live ring entry and every log entry from the head on is reduced by the
+// shift.  All of them are at or after the last window's start, which is at or
+// after the shift; saturation only guards entries a counted overflow left
+// behind.  Runs between steps, outside the captured graph.
+__global__ void k_st_rebase(StreamDev d, uint32_t shift) {
+    const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t gsz = (int64_t)gridDim.x * blockDim.x;
+    const uint32_t R = (uint32_t)d.R;
+    for (int64_t p = gid; p < d.npix; p += gsz) {
+        const uint32_t h = d.head[p], c = d.count[p];
+        uint32_t* rt = d.ring_t + p * (int64_t)R;
+        for (uint32_t k = 0; k < c; ++k) {
+            const uint32_t slot = (h + k) & (R - 1);
+            const uint32_t v = rt[slot];
+            rt[slot] = v >= shift ? v - shift : 0u;
+        }
+    }
+    const unsigned long long lh = d.log_ht[0], lt = d.log_ht[1];
+    for (unsigned long long k = lh + (unsigned long long)gid; k < lt; k += (unsigned long long)gsz) {
+        const uint32_t v = d.log_t[k & d.log_mask];
+        d.log_t[k & d.log_mask] = v >= shift ? v - shift : 0u;
+    }
+    if (gid == 0) d.epoch[0] += (int64_t)shift;
 }
 
 }  // namespace ddhf
@@ -300,7 +342,7 @@ struct ddhf_stream {
     ddhf_box_t* boxes_dev;
     int32_t* nb_dev;
     ddhf_box_t* boxes_host;
-    int32_t* nb_host;     // [4]: boxes, active, touched, touched-active
+    int32_t* nb_host;     // [8]: boxes, active, touched, touched-active, dropped candidates
     StageHdr* hdr;
     uint16_t *hx, *hy;
     int8_t* hp;
@@ -309,6 +351,10 @@ struct ddhf_stream {
     hipGraphExec_t exec;
     bool graph_ready;
     int64_t last_t;
+    int64_t epoch;        // host copy of the device epoch
+    int64_t t_per;        // grid period (us): epoch shifts are multiples of it
+    int64_t prev_t_now;   // window end of the last step (INT64_MIN before the first)
+    int64_t rebases;
     // host record of recent steps (t_now, accepted count) to bound the event log
     int64_t hist_t[1024];
     int32_t hist_n[1024];
@@ -343,6 +389,7 @@ static int stream_layout(ddhf_stream* st, Arena& dv, Arena& hs) {
     d.log_pix = dv.take<uint32_t>(lc);
     d.log_t = dv.take<uint32_t>(lc);
     d.log_ht = dv.take<unsigned long long>(2);
+    d.epoch = dv.take<int64_t>(2);
     d.step = dv.take<uint32_t>(4);
     d.stats = dv.take<unsigned long long>(8);
     d.keys = dv.take<uint32_t>(ms);
@@ -400,7 +447,7 @@ static int stream_layout(ddhf_stream* st, Arena& dv, Arena& hs) {
     st->hp = hs.take<int8_t>(ms);
     st->ht = hs.take<int64_t>(ms);
     st->boxes_host = hs.take<ddhf_box_t>(c.max_boxes > 0 ? c.max_boxes : 1);
-    st->nb_host = hs.take<int32_t>(4);
+    st->nb_host = hs.take<int32_t>(8);
     return DDHF_OK;
 }
 
@@ -465,7 +512,7 @@ static int stream_enqueue(ddhf_stream* st, hipStream_t s) {
     return DDHF_OK;
 }
 
-__global__ void k_st_init(StreamDev d, int32_t mt) {
+__global__ void k_st_init(StreamDev d, int32_t mt, int64_t epoch) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < d.npix) {
         d.head[i] = 0;
@@ -478,6 +525,7 @@ __global__ void k_st_init(StreamDev d, int32_t mt) {
     }
     if (i < mt) d.iota[i] = (int32_t)i;
     if (i < 2) d.log_ht[i] = 0;
+    if (i < 2) d.epoch[i] = i == 0 ? epoch : 0;
     if (i < 4) d.step[i] = 0;
     if (i < 8) d.stats[i] = 0;
 }
@@ -503,7 +551,15 @@ extern "C" int ddhf_stream_create(const ddhf_stream_cfg_t* cfg, ddhf_stream_t** 
     d.K = c.grid.K;
     d.n_min = c.params.n_min;
     d.T_w = c.T_w_us;
-    d.origin = c.t_origin_us;
+    st->epoch = c.t_origin_us;
+    {
+        // all grid frequencies are multiples of g = gcd(f0, df) mHz, so a shift
+        // S keeps every residue (f S) mod 1e9 = 0 iff S is a multiple of
+        // 1e9 / gcd(1e9, g) us (at most 1e9 us)
+        const uint64_t g = gcd_u64((uint64_t)c.grid.f0, (uint64_t)c.grid.df);
+        st->t_per = (int64_t)(1000000000ull / gcd_u64(1000000000ull, g));
+    }
+    st->prev_t_now = INT64_MIN;
     Arena mdv(nullptr, 0), mhs(nullptr, 0);
     int rc = stream_layout(st, mdv, mhs);
     if (rc) { delete st; return rc; }
@@ -530,7 +586,7 @@ extern "C" int ddhf_stream_create(const ddhf_stream_cfg_t* cfg, ddhf_stream_t** 
     }
     const int64_t n_init = (int64_t)d.npix > d.max_touched ? d.npix : d.max_touched;
     hipLaunchKernelGGL(k_st_init, dim3(blocks_for(n_init, 256)), dim3(256), 0, st->s_own, d,
-                       d.max_touched);
+                       d.max_touched, st->epoch);
     if (hipGetLastError() != hipSuccess || hipStreamSynchronize(st->s_own) != hipSuccess) {
         ddhf_stream_destroy(st);
         return DDHF_EHIP;
@@ -574,6 +630,28 @@ extern "C" int ddhf_stream_step(ddhf_stream_t* st, int64_t t_now_us, int32_t use
                                 ddhf_box_t* boxes_host, int32_t max_boxes, int32_t* n_boxes_host) {
     if (!st || max_boxes < 0 || (max_boxes > 0 && !boxes_host)) return DDHF_EINVAL;
     if (t_now_us < st->last_t) return DDHF_EINVAL;
+    if (st->prev_t_now != INT64_MIN && t_now_us < st->prev_t_now) return DDHF_EINVAL;
+    // Stored times are 32-bit offsets from the epoch.  From 2^31 us past it,
+    // the epoch moves to the last window start rounded down to a grid period
+    // (every stored time is at or after that start), which leaves all phases
+    // exactly as they were.
+    const int64_t kRebaseAt = (int64_t)1 << 31;
+    if (t_now_us - st->epoch >= kRebaseAt) {
+        const int64_t ref = st->prev_t_now != INT64_MIN ? st->prev_t_now : t_now_us;
+        const int64_t lo = ref - st->cfg.T_w_us - st->epoch;
+        const int64_t shift = lo > 0 ? lo / st->t_per * st->t_per : 0;
+        if (shift > 0) {
+            if (shift > (int64_t)UINT32_MAX) return DDHF_EINVAL;
+            hipLaunchKernelGGL(k_st_rebase, dim3(1024), dim3(256), 0, st->s_own, st->d,
+                               (uint32_t)shift);
+            DDHF_LAUNCH_CHECK();
+            st->epoch += shift;
+            st->rebases += 1;
+        }
+    }
+    // a window end (and with it every accepted time) must be within 2^32 us of
+    // the epoch: only a gap of more than about 2^31 us between two steps fails
+    if (t_now_us - st->epoch >= ((int64_t)1 << 32) - 1) return DDHF_EINVAL;
     // the log must hold every event of the window plus this step's
     int64_t in_window = st->hdr->n;
     int32_t counted = 0;
@@ -614,12 +692,15 @@ extern "C" int ddhf_stream_step(ddhf_stream_t* st, int64_t t_now_us, int32_t use
         if (rc) return rc;
     }
     DDHF_TRY_HIP(hipStreamSynchronize(s));
+    st->prev_t_now = t_now_us;
     st->hdr->n = 0;
     const int32_t n = st->nb_host[0];
     const int32_t k = n < max_boxes ? n : max_boxes;
     const int32_t kk = k < st->cfg.max_boxes ? k : st->cfg.max_boxes;
     if (kk > 0) memcpy(boxes_host, st->boxes_host, sizeof(ddhf_box_t) * kk);
     if (n_boxes_host) *n_boxes_host = n;
+    // outputs are complete up to the limits; say so when a limit cut them
+    if (n > kk || st->nb_host[4] > 0) return DDHF_ETRUNC;
     return DDHF_OK;
 }
 
@@ -635,6 +716,7 @@ extern "C" int ddhf_stream_stats(ddhf_stream_t* st, ddhf_stream_stats_t* out) {
     out->n_active = st->nb_host[1];
     out->n_touched = st->nb_host[2];
     out->n_recomputed = st->nb_host[3];
+    out->epoch_shifts = (int32_t)st->rebases;
     return DDHF_OK;
 }
 

@@ -26,7 +26,7 @@ class StreamStats(C.Structure):
     _fields_ = [("steps", C.c_int64), ("events_accepted", C.c_int64),
                 ("events_rejected", C.c_int64), ("ring_overflow", C.c_int64),
                 ("touched_overflow", C.c_int64), ("n_active", C.c_int32),
-                ("n_touched", C.c_int32), ("n_recomputed", C.c_int32), ("reserved", C.c_int32)]
+                ("n_touched", C.c_int32), ("n_recomputed", C.c_int32), ("epoch_shifts", C.c_int32)]
 
 
 def _np_ptr(a):
@@ -68,7 +68,10 @@ class Stream:
     def step(self, t_now_us: int, use_graph: bool = True):
         rc = D.lib().ddhf_stream_step(self._h, C.c_int64(t_now_us), C.c_int32(int(use_graph)),
                                       self._boxes, C.c_int32(self.max_boxes), C.byref(self._nb))
-        D._check(rc, "ddhf_stream_step")
+        # DDHF_ETRUNC: outputs are complete up to the limits (kept as a flag)
+        self.truncated = rc == D.DDHF_ETRUNC
+        if not self.truncated:
+            D._check(rc, "ddhf_stream_step")
         n = min(self._nb.value, self.max_boxes)
         return [dict((f, getattr(b, f)) for f, _ in D.Box._fields_) for b in self._boxes[:n]], \
             self._nb.value

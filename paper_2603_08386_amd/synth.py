@@ -312,6 +312,50 @@ def random_window(seed: int, W: int, H: int, T_w: int, n: int, grid: Grid,
                   np.zeros((H, W), bool), dict(name="random", seed=seed))
 
 
+def periodic_blob_window(T_w: int = 33_333, periods: int = 10, duty: float = 0.15,
+                         burst: int = 3, W: int = 32, H: int = 32, x0: int = 10,
+                         y0: int = 10, size: int = 3, mode_grid: bool = True,
+                         noise_per_px: int = 40, seed: int = 17) -> Window:
+    """A size x size blob of pixels whose occlusion edges repeat exactly
+    `periods` times in a window of T_w us (period T = T_w / periods, e.g.
+    3333.3 us = 300.003 Hz for a 30 FPS window): OFF bursts at
+    phi_p + m T and ON bursts at phi_p + (m + duty) T, each burst event with
+    N(0, 20 us) jitter, plus noise_per_px events of random polarity at uniform
+    times in every blob pixel (a flat spectral floor).  mode_grid selects integer modes k = 0..63 over the
+    window (0-1.9 kHz at 30 FPS); otherwise 1-1000 Hz at 1 Hz."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    period = T_w / periods
+    xs, ys, ps, ts = [], [], [], []
+    for j in range(size):
+        for i in range(size):
+            phi = 97.0 + 211.0 * (j * size + i)
+            for m in range(-1, periods + 1):
+                for t_e, pol in ((phi + m * period, -1), (phi + (m + duty) * period, 1)):
+                    for _ in range(burst):
+                        xs.append(x0 + i); ys.append(y0 + j); ps.append(pol)
+                        ts.append(t_e + rng.normal(0.0, JITTER_US))
+            for _ in range(noise_per_px):
+                xs.append(x0 + i); ys.append(y0 + j)
+                ps.append(1 if rng.random() < 0.5 else -1)
+                ts.append(rng.uniform(0.0, T_w))
+    x = np.array(xs, np.int64); y = np.array(ys, np.int64)
+    t = np.rint(np.array(ts)).astype(np.int64)
+    p = np.array(ps, np.int8)
+    keep = (t >= 0) & (t < T_w)
+    x, y, p, t = x[keep], y[keep], p[keep], t[keep]
+    o = np.argsort(t, kind="stable")
+    if mode_grid:
+        grid = Grid(f0=0, df=1, K=64, mode=1, T_w_us=T_w)
+    else:
+        grid = Grid(f0=1000, df=1000, K=1000, mode=0, T_w_us=T_w)
+    params = Params(M=4, dk=2, h_min=3, n_min=6, tau_sf=0.89, tau_comb=1.5, a_min=4, alpha=3.0)
+    label = np.zeros((H, W), bool)
+    label[y0:y0 + size, x0:x0 + size] = True
+    return Window(W, H, T0_US, T_w, x[o].astype(np.uint16), y[o].astype(np.uint16), p[o],
+                  t[o] + T0_US, grid, params, label,
+                  dict(name="periodic_blob", f_hz=1e6 / period))
+
+
 def soft_comb_batch(n_windows: int = 64, base_seed: int = 400) -> List[Window]:
     """Labelled 346x260 windows (one medium window per seed)."""
     return [medium_window(seed=base_seed + i) for i in range(n_windows)]

@@ -370,6 +370,46 @@ def test_detect_on_oracle_scores_tiny():
     assert n >= 1
 
 
+def test_detect_candidate_cap_is_deterministic():
+    """4096 separate 3x3 components (alpha = 0: nothing merges) against a cap of
+    1024 merge candidates: the device keeps the 1024 of smallest label, which
+    for square blobs are the oracle's first 1024 boxes in its (y0, x0) order;
+    n_boxes[1] counts the other 3072, and two runs give the same bits."""
+    W = H = 256
+    blobs = [(4 * i + 1, 4 * j + 1) for j in range(64) for i in range(64)]
+    on = np.zeros((H, W), bool)
+    for (x, y) in blobs:
+        on[y:y + 3, x:x + 3] = True
+    counts = np.where(on.ravel(), 8, 0)
+    row_ptr = np.concatenate([[0], np.cumsum(counts)]).astype(np.int32)
+    active = np.flatnonzero(counts >= 6).astype(np.int32)
+    sf = np.full(active.size, 0.5)
+    snr = 2.0 + (active % 97) / 10.0
+    b = (active % 3000).astype(np.int32)
+    grid = Grid(f0=10_000, df=1000, K=3991)
+    prm = Params(a_min=4, alpha=0.0)
+    banner("detect candidate cap")
+    runs = [run_detect(active, row_ptr, sf.astype(np.float32), snr.astype(np.float32), b, W, H,
+                       grid, prm, max_boxes=1024) for _ in range(2)]
+    m, lab, boxes, n, dropped = runs[0]
+    assert n == D.DDHF_DETECT_MAX_CANDIDATES and dropped == len(blobs) - n
+    assert boxes == runs[1][2] and (n, dropped) == runs[1][3:]
+    tau = Params(**{**prm.__dict__})
+    tau.tau_sf, tau.tau_comb = float(np.float32(prm.tau_sf)), float(np.float32(prm.tau_comb))
+    m64, lab64, boxes64, n64 = oracle.detect(active, row_ptr, sf.astype(np.float32).astype(np.float64),
+                                             snr.astype(np.float32).astype(np.float64), b, W, H,
+                                             grid, tau, max_boxes=4096)
+    assert n64 == len(blobs)
+    assert np.array_equal(m, m64) and np.array_equal(lab, lab64)   # always complete
+    for g1, o1 in zip(boxes, boxes64[:n]):
+        for k in ["x0", "y0", "x1", "y1", "n_px", "rep_pixel", "rep_snr"]:
+            assert g1[k] == o1[k], (k, g1, o1)
+    # fewer output slots than boxes: the first max_boxes in the same order
+    _, _, few, n2, _ = run_detect(active, row_ptr, sf.astype(np.float32), snr.astype(np.float32),
+                                  b, W, H, grid, prm, max_boxes=100)
+    assert n2 == n and few == boxes[:100]
+
+
 def test_detect_empty():
     grid = Grid(f0=10_000, df=500, K=3981)
     m, lab, boxes, n, _ = run_detect(np.zeros(0, np.int32), np.zeros(17, np.int32), np.zeros(0),
@@ -407,6 +447,80 @@ def test_end_to_end_tiny():
                [(q["x0"], q["y0"], q["x1"], q["y1"], q["n_px"]) for q in boxes64]
     # the single synthetic drone is found
     assert n >= 1
+
+
+def e2e_sampled(win, g, rows_extra=None, n_strat=60, n_rot=150, seed=0, n_bins=80):
+    """Events -> mask on the device against events -> FP64 NDFT -> FP64
+    flatness and comb on the oracle (no FP32 spectra in the oracle's chain),
+    on a stratified sample of active pixels plus rotor (label) pixels: scores
+    within FP32 tolerance, the mask bit equal except within 1e-3 of a threshold,
+    and the dominant bin where the oracle's top two scores differ by > 1e-3."""
+    r = oracle_window(win)
+    rp, act64 = r["row_ptr"], r["active"]
+    act = to_np(g.active, g.n_active)
+    order = np.argsort(act, kind="stable")
+    assert np.array_equal(act[order], act64)
+    counts = rp[act64 + 1] - rp[act64]
+    rng = np.random.default_rng(seed)
+    rows = stratified_sample(counts, n_strat, rng)
+    rot = np.flatnonzero(win.label.ravel()[act64])
+    if rot.size > n_rot:
+        rot = rng.choice(rot, n_rot, replace=False)
+    rows = np.unique(np.concatenate([rows, rot] + ([rows_extra] if rows_extra is not None else [])))
+    q = act64[rows]
+    P64 = oracle.ndft_power(rp, r["t_rel"], r["a"], q, win.grid)
+    sf64, snr64, b64 = oracle.score_rows(P64, win.grid, win.params)
+    u = order[rows]                      # device row of each sampled pixel
+    sf, snr, b = to_np(g.sf, g.n_active)[u], to_np(g.snr, g.n_active)[u], to_np(g.bin, g.n_active)[u]
+    assert np.allclose(sf, sf64, rtol=1e-3, atol=1e-6)
+    assert np.allclose(snr, snr64, rtol=1e-3, atol=1e-6)
+    prm = win.params
+    near = near_threshold(sf64, snr64, prm)
+    m64 = (sf64 <= prm.tau_sf) & (snr64 >= prm.tau_comb)
+    mask = to_np(g.mask)[q].astype(bool)
+    assert np.array_equal(mask[~near], m64[~near])
+    for i in range(min(rows.size, n_bins)):
+        _, bb, all64 = oracle.comb_score(P64[i], win.grid, prm, want_all=True)
+        top = np.sort(all64)[::-1]
+        if top.size < 2 or top[0] > (1 + 1e-3) * top[1]:
+            assert b[i] == bb, (q[i], b[i], bb)
+    return rows.size, int(rot.size), int(m64.sum())
+
+
+def test_end_to_end_medium_sampled():
+    """346x260, 50 ms, 4 drones + clutter band + noise: the whole device path
+    (index, NDFT, flatness, comb, mask) against the FP64 oracle chain."""
+    win = synth.medium_window(2)
+    banner(f"end to end medium n={win.n}")
+    g = D.window_from_synth(win, device=DEV)
+    boxes, n, dropped = g.run()
+    torch.cuda.synchronize()
+    n_rows, n_rot, n_on = e2e_sampled(win, g)
+    banner(f"  {n_rows} pixels ({n_rot} rotor, {n_on} on the mask), {n} boxes")
+    assert n_rot >= 100 and n_on >= 50 and n >= 4
+
+
+def test_end_to_end_mode_grid_30fps():
+    """Integer modes over a 33,333 us window (Sec. 3.5's normalised
+    timestamps): device boxes equal the oracle's, and the box frequency is the
+    generator's 300.003 Hz."""
+    win = synth.periodic_blob_window()
+    banner("end to end mode grid 30 FPS")
+    g = D.window_from_synth(win, device=DEV)
+    boxes, n, dropped = g.run()
+    r = oracle_window(win)
+    P64 = oracle.ndft_power(r["row_ptr"], r["t_rel"], r["a"], r["active"], win.grid)
+    sf, snr, b = oracle.score_rows(P64, win.grid, win.params)
+    m64, lab64, boxes64, n64 = oracle.detect(r["active"], r["row_ptr"], sf, snr, b, win.W, win.H,
+                                             win.grid, win.params)
+    assert not near_threshold(sf, snr, win.params).any()
+    assert np.array_equal(to_np(g.mask), m64) and np.array_equal(to_np(g.labels), lab64)
+    assert np.array_equal(to_np(g.bin, g.n_active), b)
+    assert n == n64 == 1
+    for k in ["x0", "y0", "x1", "y1", "n_px"]:
+        assert boxes[0][k] == boxes64[0][k]
+    assert boxes[0]["f_dom_hz"] == pytest.approx(win.meta["f_hz"], rel=1e-6)
+    assert boxes[0]["f_dom_hz"] == boxes64[0]["f_dom_hz"]
 
 
 # ---------------------------------------------------------------------------
@@ -520,6 +634,12 @@ def test_bench_launch_large_sampled():
     n = detect_compare(act, rp, sf.astype(np.float64), snr.astype(np.float64), b, win.W, win.H,
                        win.grid, prm)
     assert n >= 1
+    # events -> mask through the benched launch against the oracle's FP64 chain
+    g.detect()
+    torch.cuda.synchronize()
+    n_rows, n_rot, n_on = e2e_sampled(win, g, n_strat=40, n_rot=60, seed=7, n_bins=60)
+    banner(f"  end to end: {n_rows} pixels ({n_rot} rotor, {n_on} on the mask)")
+    assert n_rot >= 50
 
 
 # ---------------------------------------------------------------------------

@@ -16,14 +16,15 @@ def test_gradient_tuning_beats_or_matches_grid_search():
     banner("tune: prepare")
     data = tune.prepare(wins, device=DEV)
     banner("tune: gradient")
-    g = tune.tune_gradient(data, steps=60)
+    g = tune.tune_gradient(data, steps=200)
     banner("tune: grid")
     r = tune.tune_grid(data, n_tau=31)
     assert g["loss"][-1] < g["loss"][0]
     print(f"gradient loss {g['loss'][0]:.4g} -> {g['loss'][-1]:.4g} acc {g['accuracy']:.4f}; "
           f"grid loss {r['loss']:.4g} acc {r['accuracy']:.4f}", flush=True)
-    # the gradient reaches the grid optimum's loss (up to a small margin) and accuracy
-    assert g["loss"][-1] <= r["loss"] * 1.05 + 2e-3
+    # the gradient tuner optimises w as well as tau, so it reaches the grid
+    # optimum's loss (2 % margin for the grid's tau resolution) and accuracy
+    assert g["loss"][-1] <= r["loss"] * 1.02
     assert g["accuracy"] >= r["accuracy"] - 0.005
     assert g["accuracy"] >= 0.9
     assert np.all(np.isfinite(g["w"].cpu().numpy()))

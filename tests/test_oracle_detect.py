@@ -6,6 +6,7 @@ import pytest
 from scipy import ndimage
 
 import oracle
+from paper_2603_08386_amd import synth
 from paper_2603_08386_amd.synth import Grid, Params
 
 GRID = Grid(f0=10_000, df=500, K=3981)
@@ -121,3 +122,41 @@ def test_empty_mask():
     prm = Params(n_min=1, tau_sf=0.5, tau_comb=1.0, a_min=1, alpha=3.0)
     mask, labels, boxes, nb = run_mask(m, prm)
     assert nb == 0 and np.all(labels == -1) and not mask.any()
+
+
+def _oracle_boxes(win):
+    r = oracle.build_pixel_index(win.x, win.y, win.p, win.t, win.W, win.H, win.t0, win.T_w)
+    act = oracle.active_pixels(r["row_ptr"], win.params.n_min)
+    P = oracle.ndft_power(r["row_ptr"], r["t_rel"], r["a"], act, win.grid)
+    sf, snr, b = oracle.score_rows(P, win.grid, win.params)
+    return oracle.detect(act, r["row_ptr"], sf, snr, b, win.W, win.H, win.grid, win.params), b
+
+
+def test_mode_grid_box_frequency_is_the_train_frequency():
+    """30 FPS window (T_w = 33,333 us) whose edges repeat exactly 10 times: on
+    the mode grid the box's dominant frequency is mode 10 in Hz, 10 / 33.333 ms
+    = 300.003 Hz -- the generator's own 1 / T; on the 1 Hz grid the same events
+    land within a bin of it (the window's main lobe is 30 Hz wide)."""
+    win = synth.periodic_blob_window()
+    (mask, labels, boxes, n), b = _oracle_boxes(win)
+    assert n == 1 and mask.sum() == 9
+    assert np.all(b == 10)                              # mode 10 in every blob pixel
+    assert boxes[0]["f_dom_hz"] == pytest.approx(win.meta["f_hz"], rel=1e-6)
+    assert boxes[0]["f_dom_hz"] == pytest.approx(300.003, abs=5e-4)
+    hz = synth.periodic_blob_window(mode_grid=False)
+    (_, _, boxes_hz, n_hz), _ = _oracle_boxes(hz)
+    assert n_hz == 1 and abs(boxes_hz[0]["f_dom_hz"] - win.meta["f_hz"]) <= 1.0
+
+
+def test_mode_grid_equals_hz_grid_when_modes_are_whole_hertz():
+    """At T_w = 40,000 us (25 FPS) mode k is exactly 25 k Hz, so the mode grid
+    k = 0..63 and the Hz grid f = 25 k Hz give the same phases, bins and boxes,
+    and both conversions to Hz give 300 Hz for a train of 12 periods."""
+    mode = synth.periodic_blob_window(T_w=40_000, periods=12)
+    hz = synth.periodic_blob_window(T_w=40_000, periods=12)
+    hz.grid = Grid(f0=0, df=25_000, K=64, mode=0, T_w_us=40_000)
+    (m1, l1, b1, n1), bins1 = _oracle_boxes(mode)
+    (m2, l2, b2, n2), bins2 = _oracle_boxes(hz)
+    assert np.array_equal(bins1, bins2) and np.all(bins1 == 12)
+    assert np.array_equal(m1, m2) and n1 == n2 == 1
+    assert b1 == b2 and b1[0]["f_dom_hz"] == 300.0
