@@ -105,16 +105,19 @@ def accuracy(data: List[Labelled], w, tau, beta) -> float:
     return hit / max(count, 1)
 
 
-def tune_gradient(data: List[Labelled], steps: int = 60, lr: float = 0.1, dtype=torch.float32):
+def tune_gradient(data: List[Labelled], steps: int = 60, lr: float = 0.1, dtype=torch.float32,
+                  tau0: Optional[float] = None):
     """Adam on scale-free parameters: w = w_raw / nh (w_raw starts at 1) and
-    tau = med + sd * theta (theta starts at 0), so one learning rate suits both
-    whatever the spectra's scale."""
+    tau = med + sd * theta (theta starts at 0, or at tau0 when given, e.g. a
+    grid-search optimum to refine), so one learning rate suits both whatever
+    the spectra's scale."""
     med, sd = _score_scale(data, dtype)
     beta = 4.0 / sd
     dev = data[0].e.device
     nh = data[0].graph.nh
     w_raw = torch.ones(nh, dtype=dtype, device=dev, requires_grad=True)
-    theta = torch.zeros(1, dtype=dtype, device=dev, requires_grad=True)
+    th0 = 0.0 if tau0 is None else (tau0 - med) / sd
+    theta = torch.full((1,), th0, dtype=dtype, device=dev, requires_grad=True)
     opt = torch.optim.Adam([w_raw, theta], lr=lr)
     hist = []
     for _ in range(steps):
