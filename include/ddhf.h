@@ -250,6 +250,27 @@ int ddhf_detect(const int32_t* active, const int32_t* row_ptr, const float* sf,
                 int32_t* labels, ddhf_box_t* boxes, int32_t max_boxes, int32_t* n_boxes, void* ws,
                 size_t ws_bytes, void* stream);
 
+/* ---- 5b. detection without a workspace ----------------------------------
+ * For callers that cannot allocate device memory: code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation.  Same
+ * arguments, results and status codes as ddhf_detect, minus (ws, ws_bytes):
+ * the scratch is a fixed device array inside the library,
+ * DDHF_DETECT_NOALLOC_BYTES (about 38 MB) on each GPU the library runs on,
+ * held until the process ends.  Frames with W * H above
+ * DDHF_DETECT_NOALLOC_MAX_PIXELS are refused with DDHF_ENOSPACE.  The first
+ * call on a device resolves the array's address there (that device must be
+ * current, and the stream must belong to it).  Every call on one GPU uses the
+ * same array and leaves its contents behind (the call clears what it needs):
+ * calls that may overlap on one GPU -- different streams or threads -- race,
+ * and the caller must serialise them.  Nothing is allocated. */
+#define DDHF_DETECT_NOALLOC_MAX_PIXELS (1 << 20)
+#define DDHF_DETECT_NOALLOC_BYTES ((size_t)37781760)
+int ddhf_detect_noalloc(const int32_t* active, const int32_t* row_ptr, const float* sf,
+                        const float* snr_best, const int32_t* bin_best, int32_t n_active,
+                        int32_t W, int32_t H, const ddhf_grid_t* grid, const ddhf_params_t* prm,
+                        uint8_t* mask, int32_t* labels, ddhf_box_t* boxes, int32_t max_boxes,
+                        int32_t* n_boxes, void* stream);
+
 /* ---- 6. soft comb score and gradients (a differentiable relaxation of the
  *         comb of Eq. 8-11 for tuning weights and thresholds) ------------ */
 

@@ -17,6 +17,8 @@
 // its union box" until a round merges nothing.
 #include "ddhf_internal.h"
 
+#include <mutex>
+
 namespace ddhf {
 
 constexpr int kMergeThreads = 1024;
@@ -626,6 +628,66 @@ int detect_run(const int32_t* active, const int32_t* row_ptr, const float* sf,
     return DDHF_OK;
 }
 }  // namespace ddhf
+
+// ---- detection with a fixed scratch array (no workspace, no allocation) ----
+// The per-pixel box accumulators and the candidate list of detect_layout for
+// the largest frame the fixed array serves.
+namespace ddhf {
+constexpr size_t cx_align(size_t v) { return (v + 255) / 256 * 256; }
+constexpr size_t detect_bytes_for(int64_t npix) {
+    return 7 * cx_align((size_t)npix * 4) + cx_align((size_t)npix * 8) +
+           cx_align((size_t)kCap * sizeof(ddhf_box_t)) + cx_align(4 * sizeof(int32_t));
+}
+constexpr size_t kScratchBytes = detect_bytes_for(DDHF_DETECT_NOALLOC_MAX_PIXELS);
+static_assert(kScratchBytes == DDHF_DETECT_NOALLOC_BYTES, "header states the scratch size");
+
+// One copy per GPU, held from the library's load on that GPU to process end.
+// Host code never names it directly: its address on a device comes from
+// hipGetSymbolAddress with that device current.
+static __device__ __align__(256) char scratch[kScratchBytes];
+
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static void* g_scratch_dev[kMaxDevices];  // device address of `scratch`, per device
+
+static int scratch_on_current_device(void** out) {
+    int dev = -1;
+    DDHF_TRY_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) return DDHF_EINVAL;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_dev[dev]) {
+        void* ptr = nullptr;
+        if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr)
+            return DDHF_EHIP;
+        g_scratch_dev[dev] = ptr;
+    }
+    *out = g_scratch_dev[dev];
+    return DDHF_OK;
+}
+}  // namespace ddhf
+
+extern "C" int ddhf_detect_noalloc(const int32_t* active, const int32_t* row_ptr, const float* sf,
+                                   const float* snr_best, const int32_t* bin_best,
+                                   int32_t n_active, int32_t W, int32_t H,
+                                   const ddhf_grid_t* grid, const ddhf_params_t* prm,
+                                   uint8_t* mask, int32_t* labels, ddhf_box_t* boxes,
+                                   int32_t max_boxes, int32_t* n_boxes, void* stream) {
+    if (W <= 0 || H <= 0) return DDHF_EINVAL;
+    if ((int64_t)W * H > DDHF_DETECT_NOALLOC_MAX_PIXELS) return DDHF_ENOSPACE;
+    if (n_active > 0 && !row_ptr) return DDHF_EINVAL;
+    {
+        Arena need(nullptr, 0);
+        DetectWs d;
+        detect_layout(need, (int64_t)W * H, &d);
+        if (need.used > kScratchBytes) return DDHF_ENOSPACE;
+    }
+    void* ws = nullptr;
+    const int rc = scratch_on_current_device(&ws);
+    if (rc != DDHF_OK) return rc;
+    return detect_run(active, row_ptr, sf, snr_best, bin_best, n_active, nullptr, W, H, grid, prm,
+                      mask, labels, boxes, max_boxes, n_boxes, ws, kScratchBytes,
+                      as_stream(stream));
+}
 
 extern "C" int ddhf_detect(const int32_t* active, const int32_t* row_ptr, const float* sf,
                            const float* snr_best, const int32_t* bin_best, int32_t n_active,

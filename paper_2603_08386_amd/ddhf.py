@@ -21,6 +21,7 @@ DDHF_GRID_HZ, DDHF_GRID_MODES = 0, 1
 DDHF_KERNEL_VALU, DDHF_KERNEL_MFMA = 0, 1
 DDHF_INDEX_TIME_SORTED = 1
 DDHF_DETECT_MAX_CANDIDATES = 1024
+DDHF_DETECT_NOALLOC_MAX_PIXELS = 1 << 20
 
 
 class DdhfError(RuntimeError):
@@ -204,6 +205,15 @@ def ddhf_detect(active, row_ptr, sf, snr_best, bin_best, n_active, W, H, grid: G
                            C.byref(prm), _p(mask), _p(labels), _p(boxes), C.c_int32(max_boxes),
                            _p(n_boxes), _p(ws), C.c_size_t(ws.numel()), _stream(stream))
     _check(rc, "ddhf_detect")
+
+
+def ddhf_detect_noalloc(active, row_ptr, sf, snr_best, bin_best, n_active, W, H, grid: Grid,
+                        prm: Params, mask, labels, boxes, max_boxes, n_boxes, stream=None):
+    rc = lib().ddhf_detect_noalloc(_p(active), _p(row_ptr), _p(sf), _p(snr_best), _p(bin_best),
+                                   C.c_int32(n_active), C.c_int32(W), C.c_int32(H),
+                                   C.byref(grid), C.byref(prm), _p(mask), _p(labels), _p(boxes),
+                                   C.c_int32(max_boxes), _p(n_boxes), _stream(stream))
+    _check(rc, "ddhf_detect_noalloc")
 
 
 # ---------------------------------------------------------------------------

@@ -63,3 +63,16 @@ def test_host_side_validation_needs_no_gpu(lib):
     # zero active pixels is a no-op that needs no pointers
     assert lib.ddhf_ndft_power(None, None, None, None, 0, C.c_int64(0), C.byref(good), None, None,
                                None, C.c_size_t(0), None) == 0
+
+
+def test_detect_noalloc_refuses_oversized_frames_on_the_host(lib):
+    """Frames above DDHF_DETECT_NOALLOC_MAX_PIXELS are refused before any device call."""
+    class Grid(C.Structure):
+        _fields_ = [("f0", C.c_int64), ("df", C.c_int64), ("K", C.c_int32), ("mode", C.c_int32),
+                    ("T_w_us", C.c_int64)]
+    g = Grid(10_000, 500, 3981, 0, 0)
+    rc = lib.ddhf_detect_noalloc(None, None, None, None, None, 0, 2048, 1024, C.byref(g), None,
+                                 None, None, None, 0, None, None)
+    assert rc == 2
+    assert lib.ddhf_detect_noalloc(None, None, None, None, None, 0, 0, 4, C.byref(g), None,
+                                   None, None, None, 0, None, None) == 1
