@@ -65,6 +65,10 @@ def parse():
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain device copy of COPY_BYTES (the known-size kernel "
                          "that FETCH_SIZE / WRITE_SIZE are scaled by) and exit")
+    ap.add_argument("--counter-summary", nargs="+", metavar="CSV",
+                    help="print per-dispatch means of every rocprofv3 --pmc counter in these "
+                         "counter_collection.csv files for the NDFT and comb kernels, with "
+                         "derived per-wave and utilisation figures, then exit")
     ap.add_argument("--traffic-summary", nargs=4,
                     metavar=("FETCH_CSV", "WRITE_CSV", "CAL_FETCH_CSV", "CAL_WRITE_CSV"),
                     help="write profiles/traffic_<kernel>_<workload>.json from rocprofv3 --pmc "
@@ -138,6 +142,57 @@ def traffic_summary(args, fetch_csv, write_csv, cal_fetch_csv, cal_write_csv):
             json.dump(rec, fo, indent=1)
             fo.write("\n")
         print(json.dumps(rec), flush=True)
+
+
+MI355X_CUS, MI355X_SIMDS, MI355X_XCDS = 256, 1024, 8
+
+
+def counter_summary(paths):
+    """Means per dispatch of each counter for the kernels of the step, and the
+    figures derived from them: VALU / LDS / SALU instructions per wave,
+    VALUBusy = SQ_ACTIVE_INST_VALU (quad-cycles summed over SIMDs) / CUs /
+    GRBM_GUI_ACTIVE of one XCD, MfmaUtil = SQ_VALU_MFMA_BUSY_CYCLES / SIMDs /
+    GRBM_GUI_ACTIVE of one XCD (rocprofv3's own definitions; GRBM_GUI_ACTIVE
+    is reported summed over the 8 XCDs)."""
+    import collections
+    import csv
+    vals = collections.defaultdict(lambda: collections.defaultdict(list))
+    for path in paths:
+        with open(path) as f:
+            for r in csv.DictReader(f):
+                name = r["Kernel_Name"]
+                if "ddhf::" not in name:
+                    continue
+                short = name.split("(")[0].replace("void ", "")
+                vals[short][r["Counter_Name"]].append(float(r["Counter_Value"]))
+    lines = []
+    for k in sorted(vals, key=lambda k: -max(sum(v) / len(v) for v in vals[k].values())):
+        c = {n: sum(v) / len(v) for n, v in vals[k].items()}
+        if not any(t in k for t in ("k_ndft", "k_comb")):
+            continue
+        lines.append(k)
+        for n in sorted(c):
+            lines.append(f"  {n:28s} {c[n]:16.6g}")
+        w = c.get("SQ_WAVES")
+        g = c.get("GRBM_GUI_ACTIVE")
+        if w:
+            for n, lab in (("SQ_INSTS_VALU", "VALU"), ("SQ_INSTS_SALU", "SALU"),
+                           ("SQ_INSTS_LDS", "LDS"), ("SQ_INSTS_MFMA", "MFMA")):
+                if n in c:
+                    lines.append(f"  -> {lab} instructions per wave  {c[n] / w:12.1f}")
+        if g:
+            g1 = g / MI355X_XCDS
+            if "SQ_ACTIVE_INST_VALU" in c:
+                lines.append(f"  -> VALUBusy %                  "
+                             f"{100 * c['SQ_ACTIVE_INST_VALU'] / MI355X_CUS / g1:12.1f}")
+            if "SQ_VALU_MFMA_BUSY_CYCLES" in c:
+                lines.append(f"  -> MfmaUtil %                  "
+                             f"{100 * c['SQ_VALU_MFMA_BUSY_CYCLES'] / MI355X_SIMDS / g1:12.1f}")
+            if "SQ_LDS_BANK_CONFLICT" in c:
+                lines.append(f"  -> LDSBankConflict %           "
+                             f"{100 * c['SQ_LDS_BANK_CONFLICT'] / MI355X_CUS / g1:12.1f}")
+            lines.append(f"  -> GRBM_GUI_ACTIVE per XCD      {g1:12.6g} cycles")
+    print("\n".join(lines), flush=True)
 
 
 def kernel_source_digest(names):
@@ -346,6 +401,9 @@ def stream_leg(args, D, synth, launch):
 
 def main():
     args = parse()
+    if args.counter_summary:
+        counter_summary(args.counter_summary)
+        return
     if args.traffic_summary:
         traffic_summary(args, *args.traffic_summary)
         return
