@@ -36,6 +36,9 @@ SOFT_FLOP_PER_EVENT_HARMONIC = 16  # forward complex MAC (8) + backward Re/Im of
 
 WORKLOADS = {
     "large_1280x720": "large_window",
+    "large_edges_1280x720": "large_edges_window",
+    "heavy_tail_1280x720": "heavy_tail_window",
+    "sparse_heavy_1280x720": "sparse_heavy_window",
     "medium_346x260": "medium_window",
     "tiny_64x64": "tiny_window",
 }
@@ -54,10 +57,14 @@ def parse():
     ap.add_argument("--cost-order", type=int, default=1)
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
                     help="target CPU time of the oracle baseline sample (0 = skip)")
-    ap.add_argument("--stream-steps", type=int, default=400, help="timed stream steps (0 = skip)")
-    ap.add_argument("--plain-frames", type=int, default=15, help="plain recompute frames timed")
-    ap.add_argument("--soft-windows", type=int, default=16,
+    ap.add_argument("--stream-steps", type=int, default=10000,
+                    help="timed stream steps (0 = skip)")
+    ap.add_argument("--stream-warmup", type=int, default=500, help="untimed stream steps")
+    ap.add_argument("--plain-frames", type=int, default=200, help="plain recompute frames timed")
+    ap.add_argument("--soft-windows", type=int, default=64,
                     help="346x260 labelled windows in the soft-comb training leg (0 = skip)")
+    ap.add_argument("--cpu-workers", type=int, default=16,
+                    help="processes of the all-cores oracle baseline (capped at the CPU count)")
     ap.add_argument("--soft-steps", type=int, default=10, help="timed soft-comb training steps")
     ap.add_argument("--autotune-cache", default=None,
                     help="JSON-lines autotuner cache: read the launch from it, or time the "
@@ -291,24 +298,47 @@ def soft_leg(args, D, synth):
     }
 
 
-def cpu_baseline(win, target_s):
-    """Oracle NDFT + flatness + comb on a uniform random sample of active pixels
-    (single thread), scaled to pixel-bins per second."""
+def _oracle_sample(args):
+    """One worker of the CPU baseline: oracle NDFT + flatness + comb on its
+    share of a fixed random order of active pixels, for about target_s
+    seconds.  Returns (pixels done, seconds)."""
     import oracle
+    ctx, worker, n_workers, target_s = args
+    r, act, grid, params = ctx
+    rng = np.random.default_rng(0)
+    order = rng.permutation(act.size)[worker::n_workers]
+    done, spent, batch = 0, 0.0, 8
+    while spent < target_s and done < order.size:
+        rows = act[order[done:done + batch]]
+        t0 = time.perf_counter()
+        P = oracle.ndft_power(r["row_ptr"], r["t_rel"], r["a"], rows, grid)
+        oracle.score_rows(P, grid, params)
+        spent += time.perf_counter() - t0
+        done += rows.size
+    return done, spent
+
+
+_ORACLE_CTX = None
+
+
+def _oracle_worker(args):
+    worker, n_workers, target_s = args
+    return _oracle_sample((_ORACLE_CTX, worker, n_workers, target_s))
+
+
+def cpu_baseline(win, target_s, workers):
+    """The FP64 oracle (NDFT + flatness + comb) on a uniform random sample of
+    active pixels of the same window, scaled to pixel-bins per second: one
+    thread, and `workers` independent processes over disjoint shards of the
+    sample (forked before the GPU is touched)."""
+    import multiprocessing as mp
+    import oracle
+    global _ORACLE_CTX
     r = oracle.build_pixel_index(win.x, win.y, win.p, win.t, win.W, win.H, win.t0, win.T_w)
     act = oracle.active_pixels(r["row_ptr"], win.params.n_min)
-    rng = np.random.default_rng(0)
     K = win.grid.K
-    done_pix, spent = 0, 0.0
-    batch = 8
-    order = rng.permutation(act.size)
-    while spent < target_s and done_pix < act.size:
-        rows = act[order[done_pix:done_pix + batch]]
-        t0 = time.perf_counter()
-        P = oracle.ndft_power(r["row_ptr"], r["t_rel"], r["a"], rows, win.grid)
-        oracle.score_rows(P, win.grid, win.params)
-        spent += time.perf_counter() - t0
-        done_pix += rows.size
+    _ORACLE_CTX = (r, act, win.grid, win.params)
+    done_pix, spent = _oracle_sample((_ORACLE_CTX, 0, 1, target_s))
     cpu = "unknown CPU"
     try:
         with open("/proc/cpuinfo") as f:
@@ -318,10 +348,22 @@ def cpu_baseline(win, target_s):
                     break
     except OSError:
         pass
-    return dict(value=done_pix * K / spent, unit="pixel*bins/s", cores=1, kind="oracle",
-                sample=f"{done_pix} uniformly sampled active pixels of the same window "
-                       f"(NDFT power + flatness + comb, FP64, one thread of {os.cpu_count()} "
-                       f"on {cpu}), {spent:.1f} s")
+    one = dict(value=done_pix * K / spent, unit="pixel*bins/s", cores=1, kind="oracle",
+               sample=f"{done_pix} uniformly sampled active pixels of the same window "
+                      f"(NDFT power + flatness + comb, FP64, one thread of {os.cpu_count()} "
+                      f"on {cpu}), {spent:.1f} s")
+    n_w = max(1, min(workers, os.cpu_count() or 1))
+    t0 = time.perf_counter()
+    with mp.get_context("fork").Pool(n_w) as pool:
+        parts = pool.map(_oracle_worker, [(w, n_w, target_s) for w in range(n_w)])
+    wall = time.perf_counter() - t0
+    pix = sum(p[0] for p in parts)
+    one["all_cores"] = dict(value=pix * K / wall, unit="pixel*bins/s", cores=n_w,
+                            kind="oracle", sample=f"{pix} pixels in {n_w} processes over "
+                                                  f"disjoint shards of the same sample order, "
+                                                  f"{wall:.1f} s wall")
+    _ORACLE_CTX = None
+    return one
 
 
 def stream_leg(args, D, synth, launch):
@@ -334,18 +376,28 @@ def stream_leg(args, D, synth, launch):
     prm = synth.Params(M=4, dk=3, h_min=4, n_min=6, tau_sf=0.89, tau_comb=1.5, a_min=49, alpha=3.0)
     gen = synth.EventStream(seed=5, W=W, H=H, rate_hz=10e6, packet_us=pkt_us)
     per_step = step_us // pkt_us
-    warm = T_w // step_us + 10
+    warm = max(args.stream_warmup, T_w // step_us + 10)
     n_steps = warm + args.stream_steps
-    packets = [gen.next_packet() for _ in range(n_steps * per_step)]
+    # one second of stream is generated and replayed shifted by whole seconds
+    pool_steps = min(n_steps, 1_000_000 // step_us)
+    pool = [gen.next_packet() for _ in range(pool_steps * per_step)]
+    cycle_us = pool_steps * step_us
+
+    def packet(i):
+        c, j = divmod(i, pool_steps * per_step)
+        x, y, p, t = pool[j]
+        return x, y, p, t + c * cycle_us
+
     st = Stream(W, H, T_w, gen.t_origin, grid, prm,
                 launch=D.make_launch(launch.kernel, launch.bins_per_lane),
                 ring_cap=256, max_step_events=32768, max_touched=32768, max_boxes=256)
     lat, boxes_seen = [], 0
     t_loop0 = None
+    n_ev = 0
     for s in range(n_steps):
         if s == warm:
             t_loop0 = time.perf_counter()
-        pk = packets[s * per_step:(s + 1) * per_step]
+        pk = [packet(s * per_step + q) for q in range(per_step)]
         for q in pk[:-1]:
             st.push(*q)
         t_a = time.perf_counter()
@@ -355,25 +407,28 @@ def stream_leg(args, D, synth, launch):
         if s >= warm:
             lat.append((t_b - t_a) * 1e3)
             boxes_seen = nb
+            n_ev += sum(int(q[3].size) for q in pk)
+        if s % 2000 == 0:
+            print(f"[bench] stream step {s}/{n_steps}", file=sys.stderr, flush=True)
     t_loop = time.perf_counter() - t_loop0
     stats = st.stats()
-    n_ev = sum(int(q[3].size) for q in packets[warm * per_step:])
     st.close()
 
-    # plain recompute of the same sliding window, every few steps
-    x = np.concatenate([q[0] for q in packets]); y = np.concatenate([q[1] for q in packets])
-    p = np.concatenate([q[2] for q in packets]); t = np.concatenate([q[3] for q in packets])
+    # plain recompute of the same sliding window, at frames spread over the run
     frames = np.linspace(warm, n_steps - 1, max(args.plain_frames, 2)).astype(int)
-    cap = 0
+    wins = []
     for s in frames:
         t_now = gen.t_origin + (s + 1) * step_us
-        cap = max(cap, int(np.sum((t >= t_now - T_w) & (t < t_now))))
+        i0 = max(0, (s + 1) * per_step - T_w // pkt_us)
+        pk = [packet(i) for i in range(i0, (s + 1) * per_step)]
+        xs = np.concatenate([q[0] for q in pk]); ys = np.concatenate([q[1] for q in pk])
+        ps = np.concatenate([q[2] for q in pk]); ts = np.concatenate([q[3] for q in pk])
+        keep = (ts >= t_now - T_w) & (ts < t_now)
+        wins.append((xs[keep], ys[keep], ps[keep], ts[keep], t_now))
+    cap = max(w[0].size for w in wins)
     g = None
     plain = []
-    for s in frames:
-        t_now = gen.t_origin + (s + 1) * step_us
-        sel = (t >= t_now - T_w) & (t < t_now)
-        xs, ys, ps, ts = x[sel], y[sel], p[sel], t[sel]
+    for (xs, ys, ps, ts, t_now) in wins:
         if g is None:
             g = D.Window(xs, ys, ps, ts, W, H, t_now - T_w, T_w, grid, prm, device="cuda:0",
                          launch=launch, capacity=cap)
@@ -386,7 +441,8 @@ def stream_leg(args, D, synth, launch):
         plain.append((t_b - t_a) * 1e3)
     return {
         "workload": "stream_1280x720_10Mevps", "window_ms": T_w / 1000, "step_ms": step_us / 1000,
-        "packet_us": pkt_us, "steps_timed": args.stream_steps,
+        "packet_us": pkt_us, "steps_timed": args.stream_steps, "steps_warmup": warm,
+        "stream_generated_s": pool_steps * step_us / 1e6,
         "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
         "mean_ms": float(np.mean(lat)),
         "steps_per_s": args.stream_steps / t_loop, "events_per_s": n_ev / t_loop,
@@ -411,18 +467,25 @@ def main():
         print(json.dumps({"error": "this build measures one GPU; multi-GPU runs are not part "
                                    "of it (see DESIGN.md: how the path would shard)"}))
         sys.exit(2)
-    import torch
-    from paper_2603_08386_amd import ddhf as D
     from paper_2603_08386_amd import synth
 
-    assert torch.cuda.is_available(), "bench.py needs a GPU"
     if args.copy_calibration:
+        import torch
+        assert torch.cuda.is_available(), "bench.py needs a GPU"
         copy_calibration()
         return
     t_gen = time.time()
     win = getattr(synth, WORKLOADS[args.workload])()
     print(f"[bench] workload {args.workload}: {win.n} events, generated in "
           f"{time.time() - t_gen:.1f}s", file=sys.stderr, flush=True)
+    cpu = None
+    if args.cpu_seconds > 0:
+        # before the GPU is touched: the all-cores leg forks worker processes
+        print("[bench] cpu baseline", file=sys.stderr, flush=True)
+        cpu = cpu_baseline(win, args.cpu_seconds, args.cpu_workers)
+    import torch
+    from paper_2603_08386_amd import ddhf as D
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
 
     if args.kernel == "auto":
         launch = None
@@ -549,9 +612,8 @@ def main():
     if args.soft_windows > 0:
         print("[bench] soft comb leg", file=sys.stderr, flush=True)
         out["soft_comb"] = soft_leg(args, D, synth)
-    if args.cpu_seconds > 0:
-        print("[bench] cpu baseline", file=sys.stderr, flush=True)
-        out["cpu_baseline"] = cpu_baseline(win, args.cpu_seconds)
+    if cpu is not None:
+        out["cpu_baseline"] = cpu
     print(json.dumps(out), flush=True)
 
 

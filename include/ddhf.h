@@ -117,8 +117,11 @@ typedef struct {
  *   split_events:  pixels with more events than this are split into event
  *                  chunks whose partial spectra are summed in a fixed order
  *                  (0 = never split);
- *   persistent:    1 = a fixed grid of waves pulls (pixel, tile, chunk) units,
- *                  heaviest first, from a device queue;
+ *   persistent:    1 = a fixed grid of waves pulls (pixel, tile, chunk) units
+ *                  from a device queue: units of pixels with at least 64 events
+ *                  (and every chunk of a split pixel) one at a time, the light
+ *                  units after them eight at a time; with a cost-ordered active
+ *                  list (ddhf_active_pixels order_by_cost) the heaviest go first;
  *   grid_waves:    persistent grid size in waves (0 = auto).
  * ddhf_autotune fills this struct. */
 enum { DDHF_KERNEL_VALU = 0, DDHF_KERNEL_MFMA = 1 };

@@ -146,8 +146,8 @@ enum { kModePlain = 0, kModeList = 1, kModeQueue = 2 };
 
 struct WorkDev {
     const Unit* units;
-    const int32_t* n_units;  // device count
-    int32_t* counter;        // queue head
+    const int32_t* n_units;  // device counts: [0] units, [1] split pixels, [2] heavy prefix
+    int32_t* counter;        // queue heads: [0] heavy units, [1] light units
     float* partials;         // [slot][tile bin][re, im]
     const int32_t* n_dev;    // plain form: device count of active pixels (nullable)
 };
@@ -158,8 +158,33 @@ struct WorkDev {
 // unit is paired with a light one.
 constexpr int kPlainUnits = 2;
 
+// Persistent form: units of pixels with at least kHeavyEvents events (and
+// every chunk of a split pixel) form the leading "heavy" part of the
+// cost-ordered unit list and are claimed one at a time; the light units after
+// them are claimed kLightBatch at a time, so a wavefront issues one queue
+// atomic per batch of light pixels.
+constexpr int kHeavyEvents = 64;
+#ifndef DDHF_LIGHT_BATCH
+#define DDHF_LIGHT_BATCH 8
+#endif
+constexpr int kLightBatch = DDHF_LIGHT_BATCH;
+
+// Queue state of a persistent wavefront, packed in one 64-bit word: bits
+// 0..31 units left in the current light batch, bits 32..60 the next unit of
+// that batch, bit 61 a claim deferred until the current unit is done, bit 62
+// the current unit is heavy, bit 63 the heavy part is used up.
+constexpr uint64_t kQPending = 1ull << 61, kQHeavy = 1ull << 62, kQHeavyDone = 1ull << 63;
+
+__device__ __forceinline__ bool queue_pending(int64_t iter) {
+    return ((uint64_t)iter & kQPending) != 0;
+}
+
 // Finds the next unit of this wavefront.  Returns false when there is none.
-template <int MODE>
+// With PREFETCH (the caller asks for the next unit before computing the
+// current one), a persistent wavefront holding a heavy unit does not claim
+// another yet: the claim is deferred (queue_pending) until that unit is done,
+// so heavy units spread over all wavefronts instead of pairing up.
+template <int MODE, bool PREFETCH = false>
 __device__ __forceinline__ bool next_unit(const WorkDev& wk, const int32_t* row_ptr,
                                           const int32_t* active, int32_t n_active, int n_wtiles,
                                           int64_t& iter, Unit& un) {
@@ -181,12 +206,46 @@ __device__ __forceinline__ bool next_unit(const WorkDev& wk, const int32_t* row_
     if (MODE == kModeList) {
         if (iter > 0) return false;
         id = blockIdx.x;
+        ++iter;
     } else {
-        int32_t v = 0;
-        if (threadIdx.x == 0) v = atomicAdd(wk.counter, 1);
-        id = __builtin_amdgcn_readfirstlane(__shfl(v, 0, 64));
+        uint64_t st = (uint64_t)iter;
+        if (PREFETCH && (st & kQHeavy)) {
+            iter = (int64_t)((st & ~kQHeavy) | kQPending);  // claim after this unit
+            return false;
+        }
+        st &= ~kQPending;
+        uint32_t left = (uint32_t)st;
+        int64_t nid = (int64_t)((st >> 32) & 0x1FFFFFFFull);
+        bool heavy_done = (st & kQHeavyDone) != 0;
+        bool heavy = false;
+        if (left == 0) {
+            const int32_t H = wk.n_units[2];
+            int32_t v = 0;
+            if (!heavy_done) {
+                if (threadIdx.x == 0) v = atomicAdd(&wk.counter[0], 1);
+                v = __builtin_amdgcn_readfirstlane(__shfl(v, 0, 64));
+                if (v < H) {
+                    nid = v;
+                    left = 1;
+                    heavy = true;
+                } else {
+                    heavy_done = true;
+                }
+            }
+            if (left == 0) {
+                if (threadIdx.x == 0) v = atomicAdd(&wk.counter[1], kLightBatch);
+                v = __builtin_amdgcn_readfirstlane(__shfl(v, 0, 64));
+                nid = (int64_t)H + v;
+                left = kLightBatch;
+            }
+        }
+        id = nid;
+        --left;
+        ++nid;
+        if (nid > 0x1FFFFFFF) nid = 0x1FFFFFFF;
+        iter = (int64_t)((heavy_done ? kQHeavyDone : 0ull) | (heavy ? kQHeavy : 0ull) |
+                         ((uint64_t)nid << 32) | left);
     }
-    ++iter;
     if (id >= *wk.n_units) return false;
     un = wk.units[id];
     return true;
@@ -362,7 +421,7 @@ __global__ __launch_bounds__(64, 2) void k_ndft_mfma(const int32_t* __restrict__
     if (have) load_event(lane, un.beg, un.end, t_rel, av, t_ld, a_ld);
     while (have) {
         Unit nx;
-        const bool have_nx = next_unit<MODE>(wk, row_ptr, active, n_active, n_wtiles, iter, nx);
+        bool have_nx = next_unit<MODE, true>(wk, row_ptr, active, n_active, n_wtiles, iter, nx);
         const int tile_base = un.wt * NB * 1024;
         const uint64_t f_tile = (uint64_t)(g.f0 + (int64_t)tile_base * g.df);
         f32x16 cre[NB], cim[NB];
@@ -434,6 +493,10 @@ __global__ __launch_bounds__(64, 2) void k_ndft_mfma(const int32_t* __restrict__
                 }
             }
         }
+        if (MODE == kModeQueue && queue_pending(iter)) {
+            have_nx = next_unit<MODE, true>(wk, row_ptr, active, n_active, n_wtiles, iter, nx);
+            if (have_nx) load_event(lane, nx.beg, nx.end, t_rel, av, t_ld, a_ld);
+        }
         un = nx;
         have = have_nx;
     }
@@ -465,12 +528,24 @@ __global__ void k_units_fill(const int32_t* __restrict__ active, const int32_t* 
                              Split* __restrict__ splits, int32_t* __restrict__ totals,
                              int32_t* __restrict__ counter) {
     const int32_t u = blockIdx.x * blockDim.x + threadIdx.x;
-    if (u == 0) *counter = 0;
+    if (u == 0) {
+        counter[0] = 0;
+        counter[1] = 0;
+    }
     if (u >= n_active) return;
     const int32_t q = active[u];
     const int32_t b = row_ptr[q], n = row_ptr[q + 1] - b;
     const int32_t ch = (split > 0 && n > split) ? (n + split - 1) / split : 1;
     const uint32_t ub = o_units[u];
+    // heavy prefix: the units before the first light pixel (one writer when the
+    // list is cost ordered; any writer leaves a valid prefix otherwise)
+    auto heavy = [&](int32_t x) {
+        const int32_t qx = active[x];
+        const int32_t nx = row_ptr[qx + 1] - row_ptr[qx];
+        return nx >= kHeavyEvents || (split > 0 && nx > split);
+    };
+    if (!heavy(u) && (u == 0 || heavy(u - 1))) totals[2] = (int32_t)ub;
+    if (u == n_active - 1 && heavy(u)) totals[2] = (int32_t)(ub + c_units[u]);
     for (int32_t c = 0; c < ch; ++c) {
         const int32_t cb = b + (int32_t)(((int64_t)n * c) / ch);
         const int32_t ce = b + (int32_t)(((int64_t)n * (c + 1)) / ch);

@@ -252,14 +252,55 @@ def _smooth_field(rng, H, W, cell=16):
     return (a * (1 - fx) + b * fx) * (1 - fy) + (c * (1 - fx) + d * fx) * fy
 
 
+def _edge_crossing_times(rng, counts, theta, T_w, step_us=10.0, sigma_px_per_ms=0.5, n_dir=32):
+    """Event times of an edge-crossing model under a shared random-walk camera
+    motion.  The camera offset o(t) is a 2-D random walk (sigma px per sqrt(ms)
+    per axis) sampled every step_us; a pixel whose local edge normal points
+    along theta sees the 1-D signal s(t) = cos(theta) o_x + sin(theta) o_y and
+    fires whenever its accumulated |ds| passes one more contrast step C,
+    C = total |ds| over the window / count, with a random phase: polarity is
+    the sign of ds at that moment.  Directions are quantised to n_dir bins, so
+    pixels of similar edge direction fire in step (structured clutter, not
+    white noise).  Returns (times us, polarity) in pixel-major order."""
+    n_t = int(T_w / step_us)
+    walk = np.cumsum(rng.normal(0.0, sigma_px_per_ms * math.sqrt(step_us / 1000.0),
+                                size=(n_t, 2)), axis=0)
+    tgrid = (np.arange(n_t) + 0.5) * step_us
+    dbin = np.mod(np.rint(theta / (2.0 * math.pi) * n_dir).astype(np.int64), n_dir)
+    ts = np.empty(int(counts.sum()))
+    ps = np.empty(ts.size, np.int8)
+    offs = np.concatenate([[0], np.cumsum(counts)])
+    for d in range(n_dir):
+        sel = np.flatnonzero(dbin == d)
+        if sel.size == 0:
+            continue
+        a = 2.0 * math.pi * d / n_dir
+        ds = np.diff(math.cos(a) * walk[:, 0] + math.sin(a) * walk[:, 1], prepend=0.0)
+        tv = np.cumsum(np.abs(ds))
+        total = tv[-1]
+        n = counts[sel]
+        phase = rng.uniform(size=sel.size)
+        # event j of pixel q: accumulated |ds| reaches (j + phase_q) total / n_q
+        j = np.arange(int(n.sum())) - np.repeat(np.cumsum(n) - n, n)
+        levels = (j + np.repeat(phase, n)) * np.repeat(total / n, n)
+        k = np.minimum(np.searchsorted(tv, levels), n_t - 1)
+        dst = np.repeat(offs[sel], n) + j
+        ts[dst] = tgrid[k] + rng.uniform(-0.5 * step_us, 0.5 * step_us, size=k.size)
+        ps[dst] = np.where(ds[k] >= 0.0, 1, -1)
+    return ts, ps
+
+
 def large_window(seed: int = 3, active_frac: float = 0.60, n_heavy: int = 16,
-                 heavy_count: int = 5000) -> Window:
+                 heavy_count: int = 5000, clutter: str = "uniform") -> Window:
     """1280x720, 100 ms, hand-held global motion: a spatially coherent 60 %
     of pixels carry clutter events with log-normal counts (median 8,
     sigma 1.28, clipped to [1, 5000]) plus n_heavy planted pixels with exactly
-    5000 events; clutter timestamps are uniform in the window (the fallback of
-    the edge-crossing model) with random polarity; 3 drones of 4 discs are
-    added. About 10 M events. Grid 10-4000 Hz at 1 Hz (3991 bins)."""
+    heavy_count events, and 3 drones of 4 discs.  Clutter timestamps are
+    uniform in the window with random polarity (clutter="uniform", the
+    fallback of the edge-crossing model), or come from the edge-crossing model
+    under a random-walk camera motion of 0.5 px/ms (clutter="edges": edge
+    normals from the gradient of the same smooth field).  About 10 M events.
+    Grid 10-4000 Hz at 1 Hz (3991 bins)."""
     rng = np.random.Generator(np.random.PCG64(seed))
     W, H, T_w = 1280, 720, 100_000
     field = _smooth_field(rng, H, W)
@@ -269,8 +310,15 @@ def large_window(seed: int = 3, active_frac: float = 0.60, n_heavy: int = 16,
     heavy = rng.choice(act.size, size=n_heavy, replace=False)
     counts[heavy] = heavy_count
     pix = np.repeat(act, counts)
-    ts = rng.uniform(0.0, T_w, size=pix.size)
-    ps = np.where(rng.random(pix.size) < 0.5, -1, 1).astype(np.int8)
+    if clutter == "uniform":
+        ts = rng.uniform(0.0, T_w, size=pix.size)
+        ps = np.where(rng.random(pix.size) < 0.5, -1, 1).astype(np.int8)
+    elif clutter == "edges":
+        gy, gx = np.gradient(field)
+        theta = np.arctan2(gy.ravel()[act], gx.ravel()[act])
+        ts, ps = _edge_crossing_times(rng, counts, theta, T_w)
+    else:
+        raise ValueError(clutter)
     parts = [(pix % W, pix // W, ps, ts)]
     label = np.zeros((H, W), bool)
     centres = [(300, 200), (700, 450), (1050, 250)]
@@ -286,9 +334,48 @@ def large_window(seed: int = 3, active_frac: float = 0.60, n_heavy: int = 16,
     grid = Grid(f0=10_000, df=1000, K=3991, mode=0, T_w_us=T_w)
     params = Params(M=4, dk=3, h_min=4, n_min=6, tau_sf=0.89, tau_comb=1.5,
                     a_min=49, alpha=3.0)
+    name = "large_1280x720" if clutter == "uniform" else "large_edges_1280x720"
     return Window(W, H, T0_US, T_w, x, y, p, t, grid, params, label,
-                  dict(name="large_1280x720", seed=seed, f_bp_hz=fbp,
-                       n_heavy=n_heavy))
+                  dict(name=name, seed=seed, f_bp_hz=fbp, n_heavy=n_heavy, clutter=clutter))
+
+
+def large_edges_window(seed: int = 3) -> Window:
+    """The 1280x720 window with edge-crossing clutter under random-walk motion."""
+    return large_window(seed, clutter="edges")
+
+
+def heavy_tail_window(seed: int = 3) -> Window:
+    """The 1280x720 window with a heavier tail: 1 % of the active pixels
+    (about 5,500) planted at exactly 5000 events, about 38 M events in all."""
+    return large_window(seed, n_heavy=5530)
+
+
+def sparse_heavy_window(seed: int = 6, n_heavy: int = 64, heavy_count: int = 5000,
+                        noise_hz: float = 3.0) -> Window:
+    """1280x720, 100 ms, few but very heavy pixels: n_heavy pixels with
+    heavy_count uniform-time events each among sparse 3 Hz/px noise (a few
+    hundred pixels reach n_min), plus the 3 drones.  The heavy pixels decide
+    the NDFT time unless they are split into event chunks."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    W, H, T_w = 1280, 720, 100_000
+    parts = [noise_events(rng, noise_hz, W, H, T_w)]
+    hp = rng.choice(W * H, size=n_heavy, replace=False)
+    pix = np.repeat(hp, heavy_count)
+    parts.append((pix % W, pix // W, np.where(rng.random(pix.size) < 0.5, -1, 1).astype(np.int8),
+                  rng.uniform(0.0, T_w, size=pix.size)))
+    label = np.zeros((H, W), bool)
+    for (dx, dy) in [(300, 200), (700, 450), (1050, 250)]:
+        for (ox, oy) in [(-8, -8), (8, -8), (-8, 8), (8, 8)]:
+            f = rng.uniform(150.0, 400.0)
+            parts.append(rotor_events(rng, dx + ox, dy + oy, 5, f / 2.0, T_w, 20, W, H))
+            px, py = disc_pixels(dx + ox, dy + oy, 5, W, H)
+            label[py, px] = True
+    x, y, p, t = _assemble(parts, W, H, T_w, T0_US, rng)
+    grid = Grid(f0=10_000, df=1000, K=3991, mode=0, T_w_us=T_w)
+    params = Params(M=4, dk=3, h_min=4, n_min=6, tau_sf=0.89, tau_comb=1.5,
+                    a_min=49, alpha=3.0)
+    return Window(W, H, T0_US, T_w, x, y, p, t, grid, params, label,
+                  dict(name="sparse_heavy_1280x720", seed=seed, n_heavy=n_heavy))
 
 
 def random_window(seed: int, W: int, H: int, T_w: int, n: int, grid: Grid,

@@ -600,6 +600,33 @@ def test_ndft_large_sampled(form):
     assert err <= TOL_P
 
 
+@pytest.mark.parametrize("form", [(1, 64, 512, 1, True), (1, 64, 512, 0, True),
+                                  (1, 64, 0, 1, True)])
+def test_ndft_sparse_heavy_forms(form):
+    """1280x720 with 64 pixels of 5000 events among sparse noise: the split
+    (chunks summed in order) and persistent (heavy units claimed one at a
+    time, light units in batches) forms against the oracle on every heavy
+    pixel it samples plus count deciles, and bit-identical to the plain form."""
+    win = synth.sparse_heavy_window()
+    banner(f"ndft sparse heavy n={win.n} form={form}")
+    g, P, act = gpu_power_form(win, *form)
+    _, Pp, actp = gpu_power_form(win, 1, 64, 0, 0, True)
+    assert np.array_equal(act, actp)
+    if form[2] == 0:
+        assert np.array_equal(P, Pp)
+    r = oracle_window(win)
+    order = np.argsort(act, kind="stable")
+    assert np.array_equal(act[order], r["active"])
+    rp = r["row_ptr"]
+    counts = rp[r["active"] + 1] - rp[r["active"]]
+    rows = stratified_sample(counts, 20, np.random.default_rng(2))
+    assert (counts[rows] == 5000).sum() >= 8
+    P64 = oracle.ndft_power(rp, r["t_rel"], r["a"], r["active"][rows], win.grid)
+    err = power_err(P[order][rows], P64, rp, r["active"][rows], r["a"])
+    banner(f"  sampled rows {rows.size} max err {err:.3e}")
+    assert err <= TOL_P
+
+
 def test_bench_launch_large_sampled():
     """The launch bench.py times (MFMA, 4096 bins per wavefront, plain,
     cost-ordered) on the 1280x720 window it times: sampled rows of the power
