@@ -620,7 +620,7 @@ def test_ndft_sparse_heavy_forms(form):
     rp = r["row_ptr"]
     counts = rp[r["active"] + 1] - rp[r["active"]]
     rows = stratified_sample(counts, 20, np.random.default_rng(2))
-    assert (counts[rows] == 5000).sum() >= 8
+    assert (counts[rows] >= 5000).sum() >= 8
     P64 = oracle.ndft_power(rp, r["t_rel"], r["a"], r["active"][rows], win.grid)
     err = power_err(P[order][rows], P64, rp, r["active"][rows], r["a"])
     banner(f"  sampled rows {rows.size} max err {err:.3e}")
