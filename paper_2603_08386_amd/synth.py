@@ -220,8 +220,10 @@ def medium_window(seed: int = 2, n_drones: int = 4) -> Window:
     # drone centres on a well separated lattice
     slots = [(70, 60), (270, 60), (70, 195), (270, 195)][:n_drones]
     fbp = []
+    drone_boxes = []
     for (dx, dy) in slots:
         offsets = [(-8, -8), (0, -8), (-8, 8), (8, 8)]  # discs 0,1 overlap (dist 8 < 2R)
+        bx = [W, H, -1, -1]
         for (ox, oy) in offsets:
             f = rng.uniform(150.0, 400.0)
             fbp.append(f)
@@ -229,6 +231,9 @@ def medium_window(seed: int = 2, n_drones: int = 4) -> Window:
             parts.append(rotor_events(rng, cx, cy, 5, f / 2.0, T_w, 20, W, H))
             px, py = disc_pixels(cx, cy, 5, W, H)
             label[py, px] = True
+            bx = [min(bx[0], px.min()), min(bx[1], py.min()), max(bx[2], px.max()),
+                  max(bx[3], py.max())]
+        drone_boxes.append(tuple(int(v) for v in bx))
     parts.append(clutter_band_events(rng, W, H, T_w))
     parts.append(noise_events(rng, 5.0, W, H, T_w))
     x, y, p, t = _assemble(parts, W, H, T_w, T0_US, rng)
@@ -236,7 +241,8 @@ def medium_window(seed: int = 2, n_drones: int = 4) -> Window:
     params = Params(M=4, dk=3, h_min=4, n_min=6, tau_sf=0.89, tau_comb=1.5,
                     a_min=49, alpha=3.0)
     return Window(W, H, T0_US, T_w, x, y, p, t, grid, params, label,
-                  dict(name="medium_346x260", seed=seed, f_bp_hz=fbp))
+                  dict(name="medium_346x260", seed=seed, f_bp_hz=fbp,
+                       drone_boxes=drone_boxes))
 
 
 def _smooth_field(rng, H, W, cell=16):
