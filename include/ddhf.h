@@ -122,7 +122,15 @@ typedef struct {
  *                  (and every chunk of a split pixel) one at a time, the light
  *                  units after them eight at a time; with a cost-ordered active
  *                  list (ddhf_active_pixels order_by_cost) the heaviest go first;
- *   grid_waves:    persistent grid size in waves (0 = auto).
+ *   grid_waves:    persistent grid size in waves (0 = auto);
+ *   nufft_min_events: pixels with at least this many events take the NUFFT
+ *                  path (0 = never): the sum of Eq. 6 over the uniform grid as
+ *                  a type-1 non-uniform FFT (the alternative Sec. 3.3 names
+ *                  for large event counts): each event spread onto 2^L >= 2K
+ *                  grid points with an exponential-of-semicircle kernel of
+ *                  width 8, an FFT of length 2^L, and a per-mode kernel
+ *                  correction.  Approximate: same error bound as the direct
+ *                  sum (below).  Needs the plain form and K <= 4096.
  * ddhf_autotune fills this struct. */
 enum { DDHF_KERNEL_VALU = 0, DDHF_KERNEL_MFMA = 1 };
 typedef struct {
@@ -131,7 +139,7 @@ typedef struct {
     int32_t split_events;
     int32_t persistent;
     int32_t grid_waves;
-    int32_t reserved;
+    int32_t nufft_min_events;
 } ddhf_launch_t;
 
 /* ---- 1. events -> pixel-sorted CSR (Sec. 3.5 "Event Processing") -------- */

@@ -1,7 +1,7 @@
 // Autotuner for the NDFT launch shape.
 //
 // Times a fixed list of candidate launches (kernel, tile, split threshold,
-// persistent or not) on the caller's own CSR with HIP events (best of five),
+// persistent or not, NUFFT threshold) on the caller's own CSR with HIP events (best of five),
 // and returns the fastest; a later candidate must be 2 % faster to displace an
 // earlier one, so near-equal launches resolve in list order.  Results are cached in a JSON-lines file keyed by the device
 // architecture, the grid, and a coarse signature of the event-count
@@ -17,13 +17,16 @@
 namespace ddhf {
 
 static const ddhf_launch_t kCandidates[] = {
-    // kernel, bins_per_lane, split_events, persistent, grid_waves, reserved
+    // kernel, bins_per_lane, split_events, persistent, grid_waves, nufft_min_events
     {DDHF_KERNEL_MFMA, 64, 0, 0, 0, 0},    {DDHF_KERNEL_MFMA, 32, 0, 0, 0, 0},
     {DDHF_KERNEL_MFMA, 16, 0, 0, 0, 0},    {DDHF_KERNEL_MFMA, 64, 0, 1, 0, 0},
     {DDHF_KERNEL_MFMA, 64, 512, 1, 0, 0},  {DDHF_KERNEL_MFMA, 64, 2048, 1, 0, 0},
     {DDHF_KERNEL_MFMA, 64, 512, 0, 0, 0},  {DDHF_KERNEL_MFMA, 32, 1024, 1, 0, 0},
     {DDHF_KERNEL_VALU, 32, 0, 0, 0, 0},    {DDHF_KERNEL_VALU, 64, 0, 0, 0, 0},
     {DDHF_KERNEL_VALU, 32, 256, 1, 0, 0},
+    // heavy pixels through the NUFFT path, direct sum for the rest
+    {DDHF_KERNEL_MFMA, 64, 0, 0, 0, 512},  {DDHF_KERNEL_MFMA, 64, 0, 0, 0, 256},
+    {DDHF_KERNEL_MFMA, 64, 0, 0, 0, 128},  {DDHF_KERNEL_MFMA, 64, 0, 0, 0, 64},
 };
 static const int kNumCandidates = (int)(sizeof(kCandidates) / sizeof(kCandidates[0]));
 
@@ -57,15 +60,18 @@ static bool cache_lookup(const char* path, const std::string& key, ddhf_launch_t
     const std::string needle = "\"key\": \"" + key + "\"";
     while (fgets(line, sizeof(line), f)) {
         if (!strstr(line, needle.c_str())) continue;
-        int k = 0, b = 0, sp = 0, pe = 0, gw = 0;
+        int k = 0, b = 0, sp = 0, pe = 0, gw = 0, nu = 0;
         const char* p = strstr(line, "\"launch\": [");
-        if (p && sscanf(p, "\"launch\": [%d, %d, %d, %d, %d]", &k, &b, &sp, &pe, &gw) == 5) {
+        const int got = p ? sscanf(p, "\"launch\": [%d, %d, %d, %d, %d, %d]", &k, &b, &sp, &pe,
+                                   &gw, &nu)
+                          : 0;
+        if (got >= 5) {
             out->kernel = k;
             out->bins_per_lane = b;
             out->split_events = sp;
             out->persistent = pe;
             out->grid_waves = gw;
-            out->reserved = 0;
+            out->nufft_min_events = got == 6 ? nu : 0;
             found = true;  // the last matching line wins
         }
     }
@@ -77,8 +83,9 @@ static void cache_store(const char* path, const std::string& key, const ddhf_lau
     if (!path) return;
     FILE* f = fopen(path, "a");
     if (!f) return;
-    fprintf(f, "{\"key\": \"%s\", \"launch\": [%d, %d, %d, %d, %d], \"ms\": %.4f}\n", key.c_str(),
-            l.kernel, l.bins_per_lane, l.split_events, l.persistent, l.grid_waves, ms);
+    fprintf(f, "{\"key\": \"%s\", \"launch\": [%d, %d, %d, %d, %d, %d], \"ms\": %.4f}\n",
+            key.c_str(), l.kernel, l.bins_per_lane, l.split_events, l.persistent, l.grid_waves,
+            l.nufft_min_events, ms);
     fclose(f);
 }
 
@@ -92,8 +99,9 @@ extern "C" int ddhf_autotune_workspace_size(int32_t n_active, int64_t n_events,
     size_t mx = 0;
     for (int i = 0; i < kNumCandidates; ++i) {
         size_t b = 0;
-        const int rc = ddhf_ndft_workspace_size(n_active, n_events, grid, &kCandidates[i], &b);
-        if (rc) return rc;
+        // candidates the grid does not allow (the NUFFT path above K = 4096) are skipped
+        if (ddhf_ndft_workspace_size(n_active, n_events, grid, &kCandidates[i], &b) != DDHF_OK)
+            continue;
         if (b > mx) mx = b;
     }
     *bytes = mx;

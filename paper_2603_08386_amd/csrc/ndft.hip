@@ -150,6 +150,8 @@ struct WorkDev {
     int32_t* counter;        // queue heads: [0] heavy units, [1] light units
     float* partials;         // [slot][tile bin][re, im]
     const int32_t* n_dev;    // plain form: device count of active pixels (nullable)
+    int32_t nufft_min;       // plain form: pixels with at least this many events are left
+                             // to the NUFFT path (0 = none)
 };
 
 // Units per wavefront in the plain form, so a wavefront loads the next unit's
@@ -189,18 +191,20 @@ __device__ __forceinline__ bool next_unit(const WorkDev& wk, const int32_t* row_
                                           const int32_t* active, int32_t n_active, int n_wtiles,
                                           int64_t& iter, Unit& un) {
     if (MODE == kModePlain) {
-        if (iter >= kPlainUnits) return false;
-        const int64_t unit = (int64_t)blockIdx.x + iter * (int64_t)gridDim.x;
-        un.u = (int32_t)(unit / n_wtiles);
-        un.wt = (int)(unit % n_wtiles);
-        const int32_t na = wk.n_dev ? *wk.n_dev : n_active;
-        if (un.u >= na || un.u >= n_active) return false;
-        const int32_t q = active[un.u];
-        un.beg = row_ptr[q];
-        un.end = row_ptr[q + 1];
-        un.slot = -1;
-        ++iter;
-        return true;
+        for (;;) {
+            if (iter >= kPlainUnits) return false;
+            const int64_t unit = (int64_t)blockIdx.x + iter * (int64_t)gridDim.x;
+            un.u = (int32_t)(unit / n_wtiles);
+            un.wt = (int)(unit % n_wtiles);
+            const int32_t na = wk.n_dev ? *wk.n_dev : n_active;
+            if (un.u >= na || un.u >= n_active) return false;
+            const int32_t q = active[un.u];
+            un.beg = row_ptr[q];
+            un.end = row_ptr[q + 1];
+            un.slot = -1;
+            ++iter;
+            if (wk.nufft_min <= 0 || un.end - un.beg < wk.nufft_min) return true;
+        }
     }
     int64_t id;
     if (MODE == kModeList) {
@@ -503,6 +507,252 @@ __global__ __launch_bounds__(64, 2) void k_ndft_mfma(const int32_t* __restrict__
 }
 
 // ---------------------------------------------------------------------------
+// NUFFT path for heavy pixels.  On the uniform grid f_j = f0 + j df the sum of
+// Eq. 6 is a type-1 non-uniform DFT: with h = floor(K / 2), k = j - h,
+//     F_j = sum_e c_e exp(i k theta_e),  theta_e = 2 pi ((df t_e) mod Q) / Q,
+//     c_e = a_e exp(i 2 pi ((f0 + h df) t_e mod Q) / Q),
+// for |k| <= K / 2.  Each event is spread onto N = 2^L >= 2K grid points
+// with the kernel phi(z) = exp(beta (sqrt(1 - (2 z / w)^2) - 1)), |z| < w / 2
+// (z in grid units, w = 8, beta = 2.3 w: an "exponential of semicircle"
+// kernel, whose aliasing error at twofold oversampling is about 1e-7); the
+// grid's FFT (positive exponent) at mode k, divided by the kernel's Fourier
+// transform Phi(k) = integral of phi(z) cos(2 pi k z / N) dz, gives F_j.
+// One 256-thread workgroup per heavy pixel: the grid lives in LDS, events are
+// spread into bit-reversed positions with integer LDS atomics on fixed-point
+// values (integer addition is associative, so the result does not depend on
+// the order in which threads add).  The unit 2^-s is set per pixel from a
+// bound on any grid value: a first pass counts events per grid cell, and
+// (largest count in w consecutive cells) x max |a_e| x 2^s < 2^30, so no
+// partial sum overflows and each term keeps FP32-like relative precision.
+// Then a
+// radix-2^2 decimation-in-time FFT runs in place, and the power of the K
+// modes is written out.  Residues and phases use the same exact integer arithmetic as
+// the direct sum; the approximation is in the kernel and FP32 only.
+// ---------------------------------------------------------------------------
+constexpr int kNuW = 8;
+constexpr double kNuBeta = 2.3 * kNuW;
+constexpr int kNuThreads = 256;
+
+__device__ __forceinline__ double nu_phi(double z) {
+    const double u = 2.0 * z / kNuW;
+    const double a = 1.0 - u * u;
+    return a > 0.0 ? exp(kNuBeta * (sqrt(a) - 1.0)) : 0.0;
+}
+
+// Twiddles tw[i] = exp(2 pi i / N), i <= N / 8 (the rest follow by symmetry),
+// and the kernel correction corr[k] = 1 / Phi(k), k <= N / 2: one workgroup
+// per k sums Simpson's rule in FP64 over [0, w / 2] (phi is even).
+constexpr int kNuSimpson = 2048;  // even number of intervals
+__global__ __launch_bounds__(256) void k_nufft_tables(int logn, float2* __restrict__ tw,
+                                                      float* __restrict__ corr) {
+    const int n = 1 << logn;
+    const int k = blockIdx.x;
+    const int tid = threadIdx.x;
+    if (k == 0) {
+        for (int i = tid; i <= n / 8; i += 256) {
+            double sv, cv;
+            sincospi(2.0 * (double)i / (double)n, &sv, &cv);
+            tw[i] = make_float2((float)cv, (float)sv);
+        }
+    }
+    const double hh = 0.5 * kNuW / kNuSimpson;
+    double acc = 0.0;
+    for (int q = tid; q <= kNuSimpson; q += 256) {
+        const double z = q * hh;
+        const double wq = (q == 0 || q == kNuSimpson) ? 1.0 : ((q & 1) ? 4.0 : 2.0);
+        acc += wq * nu_phi(z) * cospi(2.0 * (double)k * z / (double)n);
+    }
+    __shared__ double red[256 / kWave];
+    acc = wave_sum(acc);
+    if (__lane_id() == 0) red[tid / kWave] = acc;
+    __syncthreads();
+    if (tid == 0) {
+        double t = 0.0;
+        for (int w = 0; w < 256 / kWave; ++w) t += red[w];
+        corr[k] = (float)(1.0 / (2.0 * t * hh / 3.0));
+    }
+}
+
+// exp(2 pi i k / N) for 0 <= k < N / 2 from the table of k <= N / 8
+template <int N>
+__device__ __forceinline__ float2 nu_tw(const float2* t8, int k) {
+    const int oct = k / (N / 8), r = k - oct * (N / 8);
+    // octant 0: t[r]; 1: (sin, cos) of the complement; 2: i t[r]; 3: i of octant 1
+    const float2 a = t8[(oct & 1) ? N / 8 - r : r];
+    float2 v = (oct & 1) ? make_float2(a.y, a.x) : a;
+    if (oct & 2) v = make_float2(-v.y, v.x);
+    return v;
+}
+
+__global__ void k_heavy_flags(const int32_t* __restrict__ active, const int32_t* __restrict__ row_ptr,
+                              int32_t n_active, int32_t n_min, uint32_t* __restrict__ flags) {
+    const int32_t u = blockIdx.x * blockDim.x + threadIdx.x;
+    if (u >= n_active) return;
+    const int32_t q = active[u];
+    flags[u] = row_ptr[q + 1] - row_ptr[q] >= n_min ? 1u : 0u;
+}
+
+__global__ void k_heavy_scatter(const uint32_t* __restrict__ flags, const uint32_t* __restrict__ pos,
+                                int32_t n_active, int32_t* __restrict__ list,
+                                int32_t* __restrict__ n_list) {
+    const int32_t u = blockIdx.x * blockDim.x + threadIdx.x;
+    if (u >= n_active) return;
+    if (flags[u]) list[pos[u]] = u;
+    if (u == n_active - 1) *n_list = (int32_t)(pos[u] + flags[u]);
+}
+
+template <int LOGN>
+__global__ __launch_bounds__(kNuThreads) void k_nufft(const int32_t* __restrict__ row_ptr,
+                                                      const uint32_t* __restrict__ t_rel,
+                                                      const float* __restrict__ av,
+                                                      const int32_t* __restrict__ active,
+                                                      const int32_t* __restrict__ list,
+                                                      const int32_t* __restrict__ n_list,
+                                                      GridDev g, int64_t f_mid,
+                                                      const float2* __restrict__ tw,
+                                                      const float* __restrict__ corr,
+                                                      float* __restrict__ power) {
+    constexpr int N = 1 << LOGN;
+    __shared__ float2 x[N];
+    __shared__ float2 t8[N / 8 + 1];
+    __shared__ float red[kNuThreads / kWave];
+    int2* xi = (int2*)x;  // the same words as fixed-point integers while spreading
+    const int tid = threadIdx.x;
+    const int h = g.K / 2;
+    const int32_t nl = *n_list;
+    for (int i = tid; i <= N / 8; i += kNuThreads) t8[i] = tw[i];
+    for (int32_t li = blockIdx.x; li < nl; li += gridDim.x) {
+        const int32_t u = list[li];
+        const int32_t q = active[u];
+        const int32_t beg = row_ptr[q], end = row_ptr[q + 1];
+        // grid position r N / Q = l0 + f of an event, integer part exact
+        auto place = [&](uint64_t t, int64_t* l0_out, float* f_out) {
+            const uint32_t r = mod_q((uint64_t)g.df * t, g);
+            const uint64_t num = (uint64_t)r << LOGN;
+            int64_t l0 = (int64_t)((double)num * g.invQ);
+            int64_t rem = (int64_t)num - l0 * (int64_t)g.Q;
+            if (rem < 0) { rem += g.Q; --l0; }
+            if (rem >= (int64_t)g.Q) { rem -= g.Q; ++l0; }
+            *l0_out = l0;
+            *f_out = (float)((double)rem * g.invQ);
+        };
+        // ---- scale: events per cell, the largest count over w consecutive cells ----
+        for (int i = tid; i < N; i += kNuThreads) xi[i] = make_int2(0, 0);
+        __syncthreads();
+        float amax = 0.0f;
+        for (int32_t e = beg + tid; e < end; e += kNuThreads) {
+            int64_t l0;
+            float f;
+            place(t_rel[e], &l0, &f);
+            amax = fmaxf(amax, fabsf(av[e]));
+            atomicAdd(&xi[(uint32_t)l0 & (uint32_t)(N - 1)].x, 1);
+        }
+        __syncthreads();
+        int cmax = 0;
+        {
+            // grid point l takes the events of cells l - w/2 .. l + w/2 - 1
+            constexpr int C = N / kNuThreads;
+            const int c0 = tid * C;
+            int win = 0;
+#pragma unroll
+            for (int d = -kNuW / 2; d < kNuW / 2; ++d) win += xi[(c0 + d) & (N - 1)].x;
+            cmax = win;
+            for (int c = 1; c < C; ++c) {
+                win += xi[(c0 + c + kNuW / 2 - 1) & (N - 1)].x - xi[(c0 + c - kNuW / 2 - 1) & (N - 1)].x;
+                cmax = win > cmax ? win : cmax;
+            }
+        }
+        const float bound = wave_max((float)cmax * amax);
+        if (__lane_id() == 0) red[tid / kWave] = bound;
+        __syncthreads();
+        float mass = 0.0f;
+#pragma unroll
+        for (int w = 0; w < kNuThreads / kWave; ++w) mass = fmaxf(mass, red[w]);
+        int ex = 0;
+        frexpf(mass * 1.0001f + 1e-30f, &ex);      // every grid value < 2^ex
+        const int sh = 30 - ex < 60 ? 30 - ex : 60;
+        const float scale = ldexpf(1.0f, sh), inv_scale = ldexpf(1.0f, -sh);
+        for (int i = tid; i < N; i += kNuThreads) xi[i] = make_int2(0, 0);
+        __syncthreads();
+        // ---- spread: events onto the grid, bit-reversed positions ----
+        for (int32_t e = beg + tid; e < end; e += kNuThreads) {
+            const uint64_t t = t_rel[e];
+            const float a = av[e];
+            const uint32_t sres = mod_q((uint64_t)f_mid * t, g);
+            int64_t l0;
+            float f;
+            place(t, &l0, &f);
+            float sn, cs;
+            sincos_fixed((uint32_t)((double)sres * g.q32), sn, cs);
+            const float cr = a * cs, ci = a * sn;
+#pragma unroll
+            for (int d = -kNuW / 2 + 1; d <= kNuW / 2; ++d) {
+                const float z = (float)d - f;
+                const float uu = 2.0f * z / (float)kNuW;
+                const float arg = 1.0f - uu * uu;
+                const float ker = arg > 0.0f ? expf((float)kNuBeta * (sqrtf(arg) - 1.0f)) : 0.0f;
+                const uint32_t l = (uint32_t)(l0 + d) & (uint32_t)(N - 1);
+                const uint32_t lb = __brev(l) >> (32 - LOGN);
+                atomicAdd(&xi[lb].x, __float2int_rn(cr * ker * scale));
+                atomicAdd(&xi[lb].y, __float2int_rn(ci * ker * scale));
+            }
+        }
+        __syncthreads();
+        for (int i = tid; i < N; i += kNuThreads) {
+            const int2 v = xi[i];
+            x[i] = make_float2((float)v.x * inv_scale, (float)v.y * inv_scale);
+        }
+        __syncthreads();
+        // ---- FFT, positive exponent, decimation in time from bit-reversed input ----
+        int m = 1;
+        if (LOGN & 1) {
+            for (int i = tid; i < N / 2; i += kNuThreads) {
+                const float2 p0 = x[2 * i], p1 = x[2 * i + 1];
+                x[2 * i] = make_float2(p0.x + p1.x, p0.y + p1.y);
+                x[2 * i + 1] = make_float2(p0.x - p1.x, p0.y - p1.y);
+            }
+            __syncthreads();
+            m = 2;
+        }
+        for (; m < N; m *= 4) {
+            // stages of half-size m and 2m fused: elements p, p + m, p + 2m, p + 3m
+            // of each group of 4m
+            for (int i = tid; i < N / 4; i += kNuThreads) {
+                const int grp = i / m, p = i - grp * m;
+                const int i0 = grp * 4 * m + p;
+                const float2 w1 = nu_tw<N>(t8, p * (N / (2 * m)));
+                const float2 w2 = nu_tw<N>(t8, p * (N / (4 * m)));
+                const float2 w3 = nu_tw<N>(t8, (p + m) * (N / (4 * m)));
+                const float2 a0 = x[i0], a1r = x[i0 + m], a2 = x[i0 + 2 * m], a3r = x[i0 + 3 * m];
+                const float2 a1 = make_float2(a1r.x * w1.x - a1r.y * w1.y, a1r.x * w1.y + a1r.y * w1.x);
+                const float2 a3 = make_float2(a3r.x * w1.x - a3r.y * w1.y, a3r.x * w1.y + a3r.y * w1.x);
+                const float2 b0 = make_float2(a0.x + a1.x, a0.y + a1.y);
+                const float2 b1 = make_float2(a0.x - a1.x, a0.y - a1.y);
+                const float2 b2r = make_float2(a2.x + a3.x, a2.y + a3.y);
+                const float2 b3r = make_float2(a2.x - a3.x, a2.y - a3.y);
+                const float2 b2 = make_float2(b2r.x * w2.x - b2r.y * w2.y, b2r.x * w2.y + b2r.y * w2.x);
+                const float2 b3 = make_float2(b3r.x * w3.x - b3r.y * w3.y, b3r.x * w3.y + b3r.y * w3.x);
+                x[i0] = make_float2(b0.x + b2.x, b0.y + b2.y);
+                x[i0 + 2 * m] = make_float2(b0.x - b2.x, b0.y - b2.y);
+                x[i0 + m] = make_float2(b1.x + b3.x, b1.y + b3.y);
+                x[i0 + 3 * m] = make_float2(b1.x - b3.x, b1.y - b3.y);
+            }
+            __syncthreads();
+        }
+        // ---- kernel correction and power of the K modes ----
+        float* out = power + (int64_t)u * g.K;
+        for (int j = tid; j < g.K; j += kNuThreads) {
+            const int k = j - h;
+            const float2 v = x[k & (N - 1)];
+            const float c = corr[k < 0 ? -k : k];
+            const float re = v.x * c, im = v.y * c;
+            out[j] = re * re + im * im;
+        }
+        __syncthreads();
+    }
+}
+
+// ---------------------------------------------------------------------------
 // unit list, split records, combine
 // ---------------------------------------------------------------------------
 __global__ void k_units_count(const int32_t* __restrict__ active, const int32_t* __restrict__ row_ptr,
@@ -601,6 +851,7 @@ struct Plan {
     int kernel, bpl, nb, split, mode;
     int tile_bins, n_wtiles;
     int64_t max_units, max_slots, max_splits;
+    int nufft_min, nufft_logn;   // NUFFT path: threshold (0 = off) and log2 of its grid
 };
 
 static bool make_plan(const ddhf_launch_t* launch, int32_t n_active, int64_t n_events, int K,
@@ -628,12 +879,25 @@ static bool make_plan(const ddhf_launch_t* launch, int32_t n_active, int64_t n_e
     p->max_slots = chunks * p->n_wtiles;
     p->max_splits = p->split > 0 ? (n_events / (p->split + 1) + 1) : 0;
     if (p->max_splits > n_active) p->max_splits = n_active;
+    p->nufft_min = launch ? launch->nufft_min_events : 0;
+    p->nufft_logn = 0;
+    if (p->nufft_min < 0) return false;
+    if (p->nufft_min > 0) {
+        if (p->mode != kModePlain || K > 4096) return false;
+        int L = 11;
+        while ((1 << L) < 2 * K) ++L;
+        p->nufft_logn = L;
+    }
     return true;
 }
 
 struct PlanWs {
     uint32_t *c_units, *c_slots, *c_split, *o_units, *o_slots, *o_split;
     void* scan_ws;
+    uint32_t *nu_flags, *nu_pos;
+    int32_t *nu_list, *nu_count;
+    float2* nu_tw;
+    float* nu_corr;
     Unit* units;
     Split* splits;
     float* partials;
@@ -645,6 +909,15 @@ static void plan_layout(Arena& ar, const Plan& p, int32_t n_active, PlanWs* w) {
     const int64_t na = n_active > 0 ? n_active : 1;
     w->totals = ar.take<int32_t>(4);
     w->counter = ar.take<int32_t>(4);
+    if (p.nufft_min > 0) {
+        w->nu_flags = ar.take<uint32_t>(na);
+        w->nu_pos = ar.take<uint32_t>(na);
+        w->nu_list = ar.take<int32_t>(na);
+        w->nu_count = ar.take<int32_t>(4);
+        w->scan_ws = ar.take<char>(scan_ws_bytes(na));
+        w->nu_tw = ar.take<float2>(((size_t)1 << (p.nufft_logn - 3)) + 1);
+        w->nu_corr = ar.take<float>(((size_t)1 << (p.nufft_logn - 1)) + 1);
+    }
     if (p.mode == kModePlain) return;
     w->c_units = ar.take<uint32_t>(na);
     w->c_slots = ar.take<uint32_t>(na);
@@ -656,6 +929,42 @@ static void plan_layout(Arena& ar, const Plan& p, int32_t n_active, PlanWs* w) {
     w->units = ar.take<Unit>(p.max_units > 0 ? p.max_units : 1);
     w->splits = ar.take<Split>(p.max_splits > 0 ? p.max_splits : 1);
     w->partials = ar.take<float>((p.max_slots > 0 ? p.max_slots : 1) * (int64_t)p.tile_bins * 2);
+}
+
+// Heavy pixels (at least p.nufft_min events) through the NUFFT kernel; the
+// plain direct kernel has skipped them.
+static int nufft_run(const Plan& p, const PlanWs& w, const int32_t* row_ptr, const uint32_t* t_rel,
+                     const float* a, const int32_t* active, int32_t n_active, const GridDev& g,
+                     float* power, hipStream_t s) {
+    const int half = 1 << (p.nufft_logn - 1);
+    hipLaunchKernelGGL(k_nufft_tables, dim3((unsigned)(half + 1)), dim3(256), 0, s,
+                       p.nufft_logn, w.nu_tw, w.nu_corr);
+    DDHF_LAUNCH_CHECK();
+    const dim3 gb(blocks_for(n_active, 256));
+    hipLaunchKernelGGL(k_heavy_flags, gb, dim3(256), 0, s, active, row_ptr, n_active, p.nufft_min,
+                       w.nu_flags);
+    DDHF_LAUNCH_CHECK();
+    const int rc = scan_exclusive_u32(w.nu_flags, w.nu_pos, n_active, w.scan_ws, s);
+    if (rc) return rc;
+    hipLaunchKernelGGL(k_heavy_scatter, gb, dim3(256), 0, s, w.nu_flags, w.nu_pos, n_active,
+                       w.nu_list, w.nu_count);
+    DDHF_LAUNCH_CHECK();
+    const int64_t f_mid = g.f0 + (int64_t)(g.K / 2) * g.df;
+    const unsigned grid = (unsigned)(n_active < 1024 ? n_active : 1024);
+    switch (p.nufft_logn) {
+#define DDHF_NUFFT_CASE(LN)                                                                      \
+    case LN:                                                                                     \
+        hipLaunchKernelGGL(k_nufft<LN>, dim3(grid), dim3(kNuThreads), 0, s, row_ptr, t_rel, a,   \
+                           active, w.nu_list, w.nu_count, g, f_mid, w.nu_tw, w.nu_corr, power); \
+        break;
+        DDHF_NUFFT_CASE(11)
+        DDHF_NUFFT_CASE(12)
+        DDHF_NUFFT_CASE(13)
+#undef DDHF_NUFFT_CASE
+        default: return DDHF_EINVAL;
+    }
+    DDHF_LAUNCH_CHECK();
+    return DDHF_OK;
 }
 
 template <typename KernelT>
@@ -677,8 +986,9 @@ static int run_plan(const Plan& p, const PlanWs& w, KernelPlain kp, KernelList k
                     const int32_t* row_ptr, const uint32_t* t_rel, const float* a,
                     const int32_t* active, int32_t n_active, const GridDev& g, float* power,
                     int grid_waves, hipStream_t s, const int32_t* n_dev) {
-    WorkDev wk{w.units, w.totals, w.counter, w.partials, n_dev};
+    WorkDev wk{w.units, w.totals, w.counter, w.partials, n_dev, p.nufft_min};
     if (n_dev && p.mode != kModePlain) return DDHF_EINVAL;
+    if (n_dev && p.nufft_min > 0) return DDHF_EINVAL;
     if (p.mode == kModePlain) {
         const int64_t units = (int64_t)n_active * p.n_wtiles;
         if (units > 0x7FFFFFFFLL) return DDHF_EINVAL;
@@ -686,6 +996,7 @@ static int run_plan(const Plan& p, const PlanWs& w, KernelPlain kp, KernelList k
         hipLaunchKernelGGL(kp, dim3((unsigned)waves), dim3(64), 0, s, row_ptr, t_rel, a, active,
                            n_active, g, p.n_wtiles, power, wk);
         DDHF_LAUNCH_CHECK();
+        if (p.nufft_min > 0) return nufft_run(p, w, row_ptr, t_rel, a, active, n_active, g, power, s);
         return DDHF_OK;
     }
     const dim3 gb(blocks_for(n_active, 256));

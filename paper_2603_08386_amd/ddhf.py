@@ -56,7 +56,8 @@ class Counters(C.Structure):
 
 class Launch(C.Structure):
     _fields_ = [("kernel", C.c_int32), ("bins_per_lane", C.c_int32), ("split_events", C.c_int32),
-                ("persistent", C.c_int32), ("grid_waves", C.c_int32), ("reserved", C.c_int32)]
+                ("persistent", C.c_int32), ("grid_waves", C.c_int32),
+                ("nufft_min_events", C.c_int32)]
 
 
 BOX_DTYPE_FIELDS = [f for f, _ in Box._fields_]
@@ -103,8 +104,8 @@ def make_params(p) -> Params:
 
 
 def make_launch(kernel=DDHF_KERNEL_VALU, bins_per_lane=32, split_events=0, persistent=0,
-                grid_waves=0) -> Launch:
-    return Launch(kernel, bins_per_lane, split_events, persistent, grid_waves, 0)
+                grid_waves=0, nufft_min_events=0) -> Launch:
+    return Launch(kernel, bins_per_lane, split_events, persistent, grid_waves, nufft_min_events)
 
 
 def workspace(nbytes: int, device="cuda") -> torch.Tensor:

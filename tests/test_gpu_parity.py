@@ -542,9 +542,9 @@ FORMS = [
 ]
 
 
-def gpu_power_form(win, kernel, bpl, split, persistent, cost, grid_waves=0):
+def gpu_power_form(win, kernel, bpl, split, persistent, cost, grid_waves=0, nufft_min=0):
     launch = D.make_launch(kernel, bpl, split_events=split, persistent=persistent,
-                           grid_waves=grid_waves)
+                           grid_waves=grid_waves, nufft_min_events=nufft_min)
     g = D.Window(win.x, win.y, win.p, win.t, win.W, win.H, win.t0, win.T_w, win.grid, win.params,
                  device=DEV, launch=launch, order_by_cost=cost)
     g.index()
@@ -624,6 +624,76 @@ def test_ndft_sparse_heavy_forms(form):
     P64 = oracle.ndft_power(rp, r["t_rel"], r["a"], r["active"][rows], win.grid)
     err = power_err(P[order][rows], P64, rp, r["active"][rows], r["a"])
     banner(f"  sampled rows {rows.size} max err {err:.3e}")
+    assert err <= TOL_P
+
+
+# ---------------------------------------------------------------------------
+# NUFFT path for heavy pixels (approximate; same error bound as the direct sum)
+# ---------------------------------------------------------------------------
+
+def nufft_check(win, nufft_min, n_strat, seed=0, cost=True):
+    """Power of sampled rows (count deciles and the heaviest pixels) with the
+    NUFFT path for pixels of at least nufft_min events, against the oracle;
+    the pixels below the threshold still come from the direct sum, bit for
+    bit.  Returns (max error, number of sampled rows on the NUFFT path)."""
+    g, P, act = gpu_power_form(win, 1, 64, 0, 0, cost, nufft_min=nufft_min)
+    _, Pd, actd = gpu_power_form(win, 1, 64, 0, 0, cost)
+    assert np.array_equal(act, actd)
+    r = oracle_window(win)
+    order = np.argsort(act, kind="stable")
+    assert np.array_equal(act[order], r["active"])
+    rp = r["row_ptr"]
+    counts = rp[r["active"] + 1] - rp[r["active"]]
+    light = (rp[act + 1] - rp[act]) < nufft_min
+    assert np.array_equal(P[light], Pd[light])
+    rows = stratified_sample(counts, n_strat, np.random.default_rng(seed))
+    P64 = oracle.ndft_power(rp, r["t_rel"], r["a"], r["active"][rows], win.grid)
+    err = power_err(P[order][rows], P64, rp, r["active"][rows], r["a"])
+    return err, int((counts[rows] >= nufft_min).sum())
+
+
+def test_ndft_nufft_tiny_every_pixel():
+    """64x64, K = 1024 (grid of 2^11 points): every active pixel through the
+    NUFFT path, all rows against the oracle."""
+    win = synth.tiny_window(1)
+    banner("ndft nufft tiny, every pixel")
+    g, P, act = gpu_power_form(win, 1, 64, 0, 0, False, nufft_min=1)
+    r = oracle_window(win)
+    assert np.array_equal(act, r["active"])
+    P64 = oracle.ndft_power(r["row_ptr"], r["t_rel"], r["a"], r["active"], win.grid)
+    err = power_err(P, P64, r["row_ptr"], r["active"], r["a"])
+    banner(f"  max err {err:.3e}")
+    assert err <= TOL_P
+
+
+@pytest.mark.parametrize("nufft_min", [64, 512])
+def test_ndft_nufft_large_sampled(nufft_min):
+    """1280x720, K = 3991 (grid of 2^13 points), heavy pixels up to 5000 events."""
+    win = synth.large_window(3)
+    banner(f"ndft nufft large, pixels >= {nufft_min} events")
+    err, n_nu = nufft_check(win, nufft_min, 40)
+    banner(f"  max err {err:.3e} ({n_nu} sampled rows on the NUFFT path)")
+    assert n_nu >= 10 and err <= TOL_P
+    # deterministic: integer spreading makes two launches bit-identical
+    _, Pa, _ = gpu_power_form(win, 1, 64, 0, 0, True, nufft_min=nufft_min)
+    _, Pb, _ = gpu_power_form(win, 1, 64, 0, 0, True, nufft_min=nufft_min)
+    assert np.array_equal(Pa, Pb)
+
+
+def test_ndft_nufft_medium_and_mode_grid():
+    """346x260 with the 0.5 Hz grid (K = 3981), and the 30 FPS mode grid
+    (integer modes over a 33,333 us window, K = 64)."""
+    win = synth.medium_window(2)
+    banner("ndft nufft medium")
+    err, n_nu = nufft_check(win, 32, 30, cost=False)
+    banner(f"  medium max err {err:.3e} ({n_nu} rows on the NUFFT path)")
+    assert n_nu >= 5 and err <= TOL_P
+    win = synth.periodic_blob_window()
+    g, P, act = gpu_power_form(win, 1, 64, 0, 0, False, nufft_min=1)
+    r = oracle_window(win)
+    P64 = oracle.ndft_power(r["row_ptr"], r["t_rel"], r["a"], r["active"], win.grid)
+    err = power_err(P, P64, r["row_ptr"], r["active"], r["a"])
+    banner(f"  mode grid max err {err:.3e}")
     assert err <= TOL_P
 
 
