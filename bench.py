@@ -54,6 +54,8 @@ def parse():
     ap.add_argument("--bpl", type=int, default=64)
     ap.add_argument("--split", type=int, default=0, help="split pixels with more events")
     ap.add_argument("--persistent", type=int, default=0)
+    ap.add_argument("--nufft", type=int, default=0,
+                    help="pixels with at least this many events take the NUFFT path (0 = never)")
     ap.add_argument("--cost-order", type=int, default=1)
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
                     help="target CPU time of the oracle baseline sample (0 = skip)")
@@ -531,7 +533,7 @@ def main():
     else:
         kernel = D.DDHF_KERNEL_VALU if args.kernel == "valu" else D.DDHF_KERNEL_MFMA
         launch = D.make_launch(kernel, args.bpl, split_events=args.split,
-                               persistent=args.persistent)
+                               persistent=args.persistent, nufft_min_events=args.nufft)
     g = D.window_from_synth(win, device="cuda:0", launch=launch,
                             order_by_cost=bool(args.cost_order))
     stream = torch.cuda.current_stream()
@@ -544,7 +546,7 @@ def main():
         t0 = time.perf_counter()
         launch, best_ms = g.autotune(cache_path=args.autotune_cache)
         tune = {"launch": [launch.kernel, launch.bins_per_lane, launch.split_events,
-                           launch.persistent], "best_ms": best_ms,
+                           launch.persistent, launch.nufft_min_events], "best_ms": best_ms,
                 "seconds": time.perf_counter() - t0}
         print(f"[bench] autotuned launch {tune}", file=sys.stderr, flush=True)
 
@@ -596,10 +598,12 @@ def main():
     achieved_tflops = flops / (ndft_ms * 1e-3) / 1e12
     kname = "valu" if launch.kernel == D.DDHF_KERNEL_VALU else "mfma"
     tag, kfrag = ndft_tag(kname, launch.bins_per_lane)
+    nufft = int(launch.nufft_min_events)
     traffic = (load_traffic(f"{tag}_{args.workload}", kernel_source_digest(TRAFFIC_SOURCES["ndft"]))
-               if launch.split_events == 0 and launch.persistent == 0 else None)
+               if launch.split_events == 0 and launch.persistent == 0 and nufft == 0 else None)
     roof_ndft = {"bound": "alu" if kname == "valu" else "mfma",
-                 "kernel": kfrag, "achieved": achieved_tflops,
+                 "kernel": kfrag + (f" + k_nufft (pixels with >= {nufft} events)" if nufft else ""),
+                 "achieved": achieved_tflops,
                  "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
                  "frac": achieved_tflops / FP32_PEAK_TFLOPS, "traffic": traffic,
                  "ms": ndft_ms, "algorithmic": f"{FLOP_PER_EVENT_BIN} FLOP x {ev_bins} event-bins"}
@@ -631,7 +635,7 @@ def main():
                    "K": K, "grid_mHz": [int(win.grid.f0), int(win.grid.df)],
                    "ndft_kernel": tag, "bins_per_lane": launch.bins_per_lane,
                    "split_events": launch.split_events, "persistent": launch.persistent,
-                   "cost_order": args.cost_order, "autotune": tune},
+                   "nufft_min_events": nufft, "cost_order": args.cost_order, "autotune": tune},
         "ndft": {"ms": ndft_ms, "pixel_bins_per_s": na * K / (ndft_ms * 1e-3),
                  "event_bins_per_s": ev_bins / (ndft_ms * 1e-3),
                  "pct_fp32_peak": 100.0 * achieved_tflops / FP32_PEAK_TFLOPS},

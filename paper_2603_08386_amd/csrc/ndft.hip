@@ -542,7 +542,7 @@ __device__ __forceinline__ double nu_phi(double z) {
 // Twiddles tw[i] = exp(2 pi i / N), i <= N / 8 (the rest follow by symmetry),
 // and the kernel correction corr[k] = 1 / Phi(k), k <= N / 2: one workgroup
 // per k sums Simpson's rule in FP64 over [0, w / 2] (phi is even).
-constexpr int kNuSimpson = 2048;  // even number of intervals
+constexpr int kNuSimpson = 512;  // even number of intervals (error ~1e-10 here)
 __global__ __launch_bounds__(256) void k_nufft_tables(int logn, float2* __restrict__ tw,
                                                       float* __restrict__ corr) {
     const int n = 1 << logn;
