@@ -463,6 +463,7 @@ __device__ __forceinline__ void locate_x2(const uint32_t* h, uint32_t base1, int
 template <int MT, int DKT>
 __global__ __launch_bounds__(kFT) void k_comb_fast(const float* __restrict__ power,
                                                    int32_t n_active, CombArgs ca, int32_t i_max,
+                                                   int32_t i_all,
                                                    float* __restrict__ sf_out,
                                                    float* __restrict__ snr_out,
                                                    int32_t* __restrict__ bin_out,
@@ -739,7 +740,37 @@ __global__ __launch_bounds__(kFT) void k_comb_fast(const float* __restrict__ pow
             bool spill = false;
             int inr[kInbCap];
             int ph = -1;
-            for (int m = 1; m <= mv; ++m) {
+            if (MT > 0 && DKT >= 0 && mv == MT && i > 2 * dk) {
+                // every window inside the spectrum and disjoint (centres at
+                // least i > 2 dk apart): all reads issued together
+                constexpr int D = DKT >= 0 ? DKT : 0;
+                constexpr int MM = MT > 0 ? MT : 1;
+                float wmv[MM];
+                uint8_t cw[MM][2 * D + 1];
+#pragma unroll
+                for (int m = 1; m <= MM; ++m) {
+                    const int cm = centre_of(i, m);
+                    wmv[m - 1] = sP[padk(cm)];
+#pragma unroll
+                    for (int q = 0; q <= 2 * D; ++q) cw[m - 1][q] = sCode[padk(cm - D + q)];
+                }
+#pragma unroll
+                for (int m = 0; m < MM; ++m) {
+                    smax += wmv[m];
+#pragma unroll
+                    for (int q = 0; q <= 2 * D; ++q) {
+                        const uint8_t c = cw[m][q];
+                        below += c == kCodeBelow ? 1 : 0;
+                        if (c < kCodeCand) {
+                            if (nin < kInbCap) inr[nin++] = (int)c;
+                            else spill = true;
+                        }
+                    }
+                }
+                hsize = MM * (2 * D + 1);
+                ph = K;  // the general loop below is skipped
+            }
+            for (int m = 1; m <= mv && ph < K; ++m) {
                 const int cm = centre_of(i, m);
                 smax += sP[padk(cm)];
                 const int lo = (cm - dk) > ph + 1 ? (cm - dk) : ph + 1;
@@ -843,14 +874,28 @@ __global__ __launch_bounds__(kFT) void k_comb_fast(const float* __restrict__ pow
             }
             return mv >= ca.h_min ? smax * __builtin_amdgcn_rcpf((float)mv) : -1.0f;
         };
-        // the first kKeep rounds keep N in registers for the filter pass
+        // the first kKeep rounds keep N in registers for the filter pass; a
+        // round whose candidates all have every harmonic window inside the
+        // spectrum (i <= i_all) reads the window maxima at fixed offsets from
+        // per-harmonic bases: padk(c + kFT m r) = padk(c) + (kFT + kFT / 16) m r
         constexpr int kKeep = 8;
+        constexpr int MB = MT > 0 ? MT : 1;
+        int base[MB];
+#pragma unroll
+        for (int m = 1; m <= MB; ++m) base[m - 1] = padk(centre_of(dk + tid, m));
         float nv[kKeep];
         float lb = 0.0f;
 #pragma unroll
         for (int r = 0; r < kKeep; ++r) {
             const int i = dk + tid + r * kFT;
-            nv[r] = i <= i_max ? n_of(i) : -1.0f;
+            if (MT > 0 && dk + kFT - 1 + r * kFT <= i_all) {
+                float smax = 0.0f;
+#pragma unroll
+                for (int m = 1; m <= MB; ++m) smax += sP[base[m - 1] + (kFT + kFT / 16) * m * r];
+                nv[r] = MT >= ca.h_min ? smax * (1.0f / (float)MB) : -1.0f;
+            } else {
+                nv[r] = i <= i_max ? n_of(i) : -1.0f;
+            }
             lb = fmaxf(lb, nv[r] * r_hi);
         }
         for (int i = dk + tid + kKeep * kFT; i <= i_max; i += kFT) lb = fmaxf(lb, n_of(i) * r_hi);
@@ -953,20 +998,30 @@ int comb_run(const float* power, int32_t n_active, const int32_t* n_dev, const d
         if (i_max > ca.K - 1 - ca.dk) i_max = ca.K - 1 - ca.dk;
     }
     const int bw = ca.b_hi - ca.b_lo + 1;
+    // largest candidate whose M windows all stay in band
+    int32_t i_all = -1;
+    {
+        int64_t lo = 0, hi = i_max;
+        while (lo <= hi) {
+            const int64_t mid = (lo + hi) / 2;
+            if (centre_h(prm->M, mid) + ca.dk <= ca.K - 1) { i_all = (int32_t)mid; lo = mid + 1; }
+            else hi = mid - 1;
+        }
+    }
     if (ca.K <= 4096 && bw <= 253) {
         CombArgs cf = ca;
         cf.kpad = ((ca.K - 1) + ((ca.K - 1) >> kSegShift) + 1 + 3) / 4 * 4;  // padded bin array
         const size_t lds = (size_t)cf.kpad * 4 + (size_t)x_bytes(ca.K, bw);
         const dim3 gr((unsigned)n_active), bl(kFT);
         if (ca.M == 4 && ca.dk == 3)
-            hipLaunchKernelGGL((k_comb_fast<4, 3>), gr, bl, lds, s, power, n_active, cf, i_max, sf,
-                               snr_best, bin_best, snr_all, n_dev);
+            hipLaunchKernelGGL((k_comb_fast<4, 3>), gr, bl, lds, s, power, n_active, cf, i_max, i_all,
+                               sf, snr_best, bin_best, snr_all, n_dev);
         else if (ca.M == 5 && ca.dk == 3)
-            hipLaunchKernelGGL((k_comb_fast<5, 3>), gr, bl, lds, s, power, n_active, cf, i_max, sf,
-                               snr_best, bin_best, snr_all, n_dev);
+            hipLaunchKernelGGL((k_comb_fast<5, 3>), gr, bl, lds, s, power, n_active, cf, i_max, i_all,
+                               sf, snr_best, bin_best, snr_all, n_dev);
         else
             hipLaunchKernelGGL((k_comb_fast<-1, -1>), gr, bl, lds, s, power, n_active, cf, i_max,
-                               sf, snr_best, bin_best, snr_all, n_dev);
+                               i_all, sf, snr_best, bin_best, snr_all, n_dev);
         DDHF_LAUNCH_CHECK();
         return DDHF_OK;
     }
