@@ -14,6 +14,7 @@
 // q = r + #(window bins of rank <= q), reached by a short fixed-point
 // iteration over the (rare) window bins that fall inside the band.
 #include "ddhf_internal.h"
+#include "phase.h"
 
 namespace ddhf {
 
@@ -460,15 +461,16 @@ __device__ __forceinline__ void locate_x2(const uint32_t* h, uint32_t base1, int
     __syncthreads();
 }
 
-template <int MT, int DKT>
-__global__ __launch_bounds__(kFT) void k_comb_fast(const float* __restrict__ power,
-                                                   int32_t n_active, CombArgs ca, int32_t i_max,
-                                                   int32_t i_all,
-                                                   float* __restrict__ sf_out,
-                                                   float* __restrict__ snr_out,
-                                                   int32_t* __restrict__ bin_out,
-                                                   float* __restrict__ snr_all,
-                                                   const int32_t* __restrict__ n_dev) {
+// The fast comb of one pixel (active index u).  fill(sP) writes the pixel's
+// spectrum into the padded LDS array (bin k at padk(k), k < K) with the
+// workgroup's 256 threads; it may use the LDS after the spectrum as scratch and
+// must end with that scratch no longer read (the body clears it).
+template <int MT, int DKT, class Fill>
+__device__ __forceinline__ void comb_fast_pixel(const CombArgs& ca, int32_t u, int32_t i_max,
+                                                int32_t i_all, float* __restrict__ sf_out,
+                                                float* __restrict__ snr_out,
+                                                int32_t* __restrict__ bin_out,
+                                                float* __restrict__ snr_all, Fill&& fill) {
     extern __shared__ __align__(16) char smem[];
     float* sP = (float*)smem;                       // [kpad]: spectrum, then window maxima
     uint32_t* sX = (uint32_t*)(sP + ca.kpad);       // histograms, then codes ...
@@ -487,32 +489,17 @@ __global__ __launch_bounds__(kFT) void k_comb_fast(const float* __restrict__ pow
     const int M = MT > 0 ? MT : ca.M;
     const int dk = DKT >= 0 ? DKT : ca.dk;
     const int tid = threadIdx.x;
-    const int32_t u = blockIdx.x;
-    if (u >= n_active || (n_dev && u >= *n_dev)) return;
-    const float* row = power + (int64_t)u * K;
     const int k0 = tid * kFastItems;        // first bin of this thread's segment
     const int s0 = tid * (kFastItems + 1);  // its padded LDS index
 
-    // ---- coalesced load, transpose through LDS ------------------------------
-    {
-        float g[kFastItems];
+    fill(sP);
 #pragma unroll
-        for (int i = 0; i < kFastItems; ++i) {
-            const int k = tid + i * kFT;
-            g[i] = k < K ? row[k] : 0.0f;
-        }
-#pragma unroll
-        for (int i = 0; i < kHistWords / kFT; ++i) sX[tid + i * kFT] = 0u;
-        if (tid < kWave) s_rank[tid] = 0u;
-        if (tid == 0) {
-            l1lo = l1hi = l2lo = l2hi = Loc{0, 0};
-            s_nlist = 0;
-            s_qn = 0;
-        }
-        const int ps = padk(tid);
-#pragma unroll
-        for (int i = 0; i < kFastItems; ++i)
-            if (tid + i * kFT < K) sP[ps + i * (kFT + (kFT >> kSegShift))] = g[i];
+    for (int i = 0; i < kHistWords / kFT; ++i) sX[tid + i * kFT] = 0u;
+    if (tid < kWave) s_rank[tid] = 0u;
+    if (tid == 0) {
+        l1lo = l1hi = l2lo = l2hi = Loc{0, 0};
+        s_nlist = 0;
+        s_qn = 0;
     }
     __syncthreads();
     float v[kFastItems];
@@ -942,6 +929,170 @@ __global__ __launch_bounds__(kFT) void k_comb_fast(const float* __restrict__ pow
     }
 }
 
+// Fast comb over spectra in HBM: the row is loaded coalesced and transposed
+// into the padded LDS array (one padding word per 16 bins).
+template <int MT, int DKT>
+__global__ __launch_bounds__(kFT) void k_comb_fast(const float* __restrict__ power,
+                                                   int32_t n_active, CombArgs ca, int32_t i_max,
+                                                   int32_t i_all,
+                                                   float* __restrict__ sf_out,
+                                                   float* __restrict__ snr_out,
+                                                   int32_t* __restrict__ bin_out,
+                                                   float* __restrict__ snr_all,
+                                                   const int32_t* __restrict__ n_dev) {
+    const int32_t u = blockIdx.x;
+    if (u >= n_active || (n_dev && u >= *n_dev)) return;
+    const float* row = power + (int64_t)u * ca.K;
+    comb_fast_pixel<MT, DKT>(ca, u, i_max, i_all, sf_out, snr_out, bin_out, snr_all,
+                             [&](float* sP) {
+        const int tid = threadIdx.x;
+        float g[kFastItems];
+#pragma unroll
+        for (int i = 0; i < kFastItems; ++i) {
+            const int k = tid + i * kFT;
+            g[i] = k < ca.K ? row[k] : 0.0f;
+        }
+        const int ps = padk(tid);
+#pragma unroll
+        for (int i = 0; i < kFastItems; ++i)
+            if (tid + i * kFT < ca.K) sP[ps + i * (kFT + (kFT >> kSegShift))] = g[i];
+    });
+}
+
+// ---------------------------------------------------------------------------
+// Spectrum, flatness and comb in one kernel (Eq. 6-11, K <= 4096): the power
+// spectrum of the pixel is formed in the comb's LDS array and never reaches
+// HBM.  Wave w of the workgroup computes bins [1024 w, 1024 w + 1024) as the
+// factorised product F[1024 w + 32 b + s] = sum_e U_w[b, e] V[e, s] on the FP32
+// matrix cores (v_mfma_f32_32x32x2_f32, one event per k pair), with
+//     U_w[b, e] = a_e exp(2 pi i (A_e + (1024 w + 32 b) D_e) / Q),
+//     V[e, s]   = exp(2 pi i s D_e / Q),
+// A_e = (f0 t_e) mod Q and D_e = (df t_e) mod Q exact integer residues.  Two
+// events per step: lanes 0..31 form row / column (lane mod 32) of the even
+// event and lanes 32..63 those of the odd one; v_permlane32_swap(c, s) then
+// yields [c(0..31), s(0..31)] and [c(32..63), s(32..63)], the operands of the
+// two events, for A = (Re U | Im U) and for both B forms (Re V | -Im V) and
+// (Im V | Re V).  Events are staged 256 at a time (one per thread) in the LDS
+// that the comb later uses for its histograms.
+// ---------------------------------------------------------------------------
+struct EvFused {
+    uint32_t phiA, q1, q2;  // fractions of A and of D (q1 = F >> 16, q2 = F & 0xFFFF)
+    float a;
+};
+constexpr int kFuseChunk = kFT;
+static_assert(kFuseChunk * sizeof(EvFused) <= 4 * kHistWords, "event stage fits the histograms");
+
+// phi = phiA + m F / 2^16 (mod 2^32) for bin offsets m < 2^12, from 24-bit
+// multiply-adds; error below 2^-30 revolutions.
+__device__ __forceinline__ uint32_t frac_phase12(uint32_t phiA, uint32_t q1, uint32_t q2,
+                                                 uint32_t m) {
+    const uint32_t mm = m & 0xFFFu;
+    const uint32_t t = mm * (q1 & 0xFFFFu) + phiA;
+    const uint32_t u = mm * (q1 >> 16);
+    const uint32_t v = mm * (q2 & 0xFFFFu);
+    return t + (u << 16) + (v >> 16);
+}
+
+struct PairOps {
+    float a0, a1, br0, br1, bi0, bi1;  // A and B operands of the even and the odd event
+};
+
+__device__ __forceinline__ PairOps pair_operands(const EvFused& s, uint32_t mU, uint32_t mV) {
+    float sn, cs, vs, vc;
+    sincos_rev(frac_phase12(s.phiA, s.q1, s.q2, mU), sn, cs);
+    sincos_rev(frac_phase12(0u, s.q1, s.q2, mV), vs, vc);
+    const float uc = cs * s.a, us = sn * s.a;
+    const auto pa = __builtin_amdgcn_permlane32_swap(__float_as_uint(uc), __float_as_uint(us),
+                                                     false, false);
+    const auto pb = __builtin_amdgcn_permlane32_swap(__float_as_uint(vc), __float_as_uint(-vs),
+                                                     false, false);
+    const auto pc = __builtin_amdgcn_permlane32_swap(__float_as_uint(vs), __float_as_uint(vc),
+                                                     false, false);
+    PairOps o;
+    o.a0 = __uint_as_float(pa[0]);
+    o.a1 = __uint_as_float(pa[1]);
+    o.br0 = __uint_as_float(pb[0]);
+    o.br1 = __uint_as_float(pb[1]);
+    o.bi0 = __uint_as_float(pc[0]);
+    o.bi1 = __uint_as_float(pc[1]);
+    return o;
+}
+
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+
+template <int MT, int DKT>
+__global__ __launch_bounds__(kFT) void k_ndft_comb(const int32_t* __restrict__ row_ptr,
+                                                   const uint32_t* __restrict__ t_rel,
+                                                   const float* __restrict__ av,
+                                                   const int32_t* __restrict__ active,
+                                                   int32_t n_active, GridDev g, CombArgs ca,
+                                                   int32_t i_max, int32_t i_all,
+                                                   float* __restrict__ sf_out,
+                                                   float* __restrict__ snr_out,
+                                                   int32_t* __restrict__ bin_out) {
+    const int32_t u = blockIdx.x;
+    if (u >= n_active) return;
+    const int32_t px = active[u];
+    const int32_t beg = row_ptr[px], end = row_ptr[px + 1];
+    comb_fast_pixel<MT, DKT>(ca, u, i_max, i_all, sf_out, snr_out, bin_out, nullptr,
+                             [&](float* sP) {
+        EvFused* st = (EvFused*)(sP + ca.kpad);
+        const int tid = threadIdx.x;
+        const int lane = tid & (kWave - 1);
+        const int w = tid / kWave;
+        const int half = lane >> 5;
+        const uint32_t r32 = (uint32_t)(lane & 31);
+        const uint32_t mU = 1024u * (uint32_t)w + 32u * r32;  // U row r32 of tile w
+        const bool live = 1024 * w < ca.K;                     // wave-uniform
+        f32x16 cre, cim;
+#pragma unroll
+        for (int r = 0; r < 16; ++r) { cre[r] = 0.0f; cim[r] = 0.0f; }
+        for (int32_t c0 = beg; c0 < end; c0 += kFuseChunk) {
+            {
+                // stage: entries past the pixel's end carry zero weight
+                const int32_t e = c0 + tid;
+                EvFused s{0u, 0u, 0u, 0.0f};
+                if (e < end) {
+                    const uint64_t t = t_rel[e];
+                    const uint32_t A = mod_q((uint64_t)g.f0 * t, g);
+                    const uint32_t D = mod_q((uint64_t)g.df * t, g);
+                    const Frac f = make_frac(A, D, g);
+                    s.phiA = f.phiA;
+                    s.q1 = (uint32_t)(f.F >> 16);
+                    s.q2 = (uint32_t)(f.F & 0xFFFFu);
+                    s.a = av[e];
+                }
+                st[tid] = s;
+            }
+            __syncthreads();
+            const int ne = (end - c0) < kFuseChunk ? (end - c0) : kFuseChunk;
+            const int np = (ne + 1) >> 1;
+            if (live) {
+                // software pipelined: the next pair's operands are formed while
+                // this pair's four MFMAs run
+                PairOps o = pair_operands(st[half], mU, r32);
+                for (int k = 0; k < np; ++k) {
+                    const EvFused sn = st[2 * (k + 1 < np ? k + 1 : k) + half];
+                    cre = __builtin_amdgcn_mfma_f32_32x32x2f32(o.a0, o.br0, cre, 0, 0, 0);
+                    cim = __builtin_amdgcn_mfma_f32_32x32x2f32(o.a0, o.bi0, cim, 0, 0, 0);
+                    cre = __builtin_amdgcn_mfma_f32_32x32x2f32(o.a1, o.br1, cre, 0, 0, 0);
+                    cim = __builtin_amdgcn_mfma_f32_32x32x2f32(o.a1, o.bi1, cim, 0, 0, 0);
+                    o = pair_operands(sn, mU, r32);
+                }
+            }
+            __syncthreads();
+        }
+        // power of the wave's tile into the padded spectrum; register r holds
+        // row 8 (r / 4) + 4 half + r % 4, column lane mod 32
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+            const int row = 8 * (r >> 2) + 4 * half + (r & 3);
+            const int j = 1024 * w + 32 * row + (int)r32;
+            if (j < ca.K) sP[padk(j)] = cre[r] * cre[r] + cim[r] * cim[r];
+        }
+    });
+}
+
 static size_t comb_lds_bytes(const CombArgs& ca) {
     const int hist_words = (2 * kHistBins > ca.kpad + 4) ? 2 * kHistBins : ca.kpad + 4;
     return (size_t)ca.kpad * 4 + (size_t)ca.kpad * 2 * 2 + (size_t)hist_words * 4 +
@@ -953,17 +1104,28 @@ static size_t comb_lds_bytes(const CombArgs& ca) {
 using namespace ddhf;
 
 namespace ddhf {
-int comb_run(const float* power, int32_t n_active, const int32_t* n_dev, const ddhf_grid_t* grid,
-             const ddhf_params_t* prm, float* sf, float* snr_best, int32_t* bin_best,
-             float* snr_all, hipStream_t s) {
-    if (!grid || !prm || n_active < 0) return DDHF_EINVAL;
-    if (grid->K <= 0 || grid->K > 8192 || grid->df <= 0 || grid->f0 < 0) return DDHF_EINVAL;
+// Launch constants of the comb shared by the spectrum-reading and the fused
+// kernels: harmonic offsets, median band, and the candidate limits i_max (first
+// h_min windows in band) and i_all (all M windows in band).
+struct CombSetup {
+    CombArgs ca;
+    int32_t i_max, i_all;
+    bool fast;      // K <= 4096 and band <= 253 ranks: one thread per 16 bins
+    size_t lds;     // dynamic LDS of the fast kernels
+};
+
+static bool comb_params_ok(const ddhf_grid_t* grid, const ddhf_params_t* prm) {
+    if (!grid || !prm) return false;
+    if (grid->K <= 0 || grid->K > 8192 || grid->df <= 0 || grid->f0 < 0) return false;
     if (prm->M < 1 || prm->M > 32 || prm->dk < 0 || prm->dk > 16 || prm->h_min < 1 ||
         !(prm->eps_rel >= 0.0f))
-        return DDHF_EINVAL;
-    if (n_active == 0) return DDHF_OK;
-    if (!power || !sf || !snr_best || !bin_best) return DDHF_EINVAL;
-    CombArgs ca;
+        return false;
+    return true;
+}
+
+static CombSetup comb_setup(const ddhf_grid_t* grid, const ddhf_params_t* prm) {
+    CombSetup cs;
+    CombArgs& ca = cs.ca;
     ca.K = grid->K;
     ca.M = prm->M;
     ca.dk = prm->dk;
@@ -1008,10 +1170,29 @@ int comb_run(const float* power, int32_t n_active, const int32_t* n_dev, const d
             else hi = mid - 1;
         }
     }
-    if (ca.K <= 4096 && bw <= 253) {
-        CombArgs cf = ca;
-        cf.kpad = ((ca.K - 1) + ((ca.K - 1) >> kSegShift) + 1 + 3) / 4 * 4;  // padded bin array
-        const size_t lds = (size_t)cf.kpad * 4 + (size_t)x_bytes(ca.K, bw);
+    cs.i_max = i_max;
+    cs.i_all = i_all;
+    cs.fast = ca.K <= 4096 && bw <= 253;
+    cs.lds = 0;
+    if (cs.fast) {
+        ca.kpad = ((ca.K - 1) + ((ca.K - 1) >> kSegShift) + 1 + 3) / 4 * 4;  // padded bin array
+        cs.lds = (size_t)ca.kpad * 4 + (size_t)x_bytes(ca.K, bw);
+    }
+    return cs;
+}
+
+int comb_run(const float* power, int32_t n_active, const int32_t* n_dev, const ddhf_grid_t* grid,
+             const ddhf_params_t* prm, float* sf, float* snr_best, int32_t* bin_best,
+             float* snr_all, hipStream_t s) {
+    if (!comb_params_ok(grid, prm) || n_active < 0) return DDHF_EINVAL;
+    if (n_active == 0) return DDHF_OK;
+    if (!power || !sf || !snr_best || !bin_best) return DDHF_EINVAL;
+    const CombSetup cs = comb_setup(grid, prm);
+    const int32_t i_max = cs.i_max, i_all = cs.i_all;
+    if (cs.fast) {
+        const CombArgs& cf = cs.ca;
+        const CombArgs& ca = cs.ca;
+        const size_t lds = cs.lds;
         const dim3 gr((unsigned)n_active), bl(kFT);
         if (ca.M == 4 && ca.dk == 3)
             hipLaunchKernelGGL((k_comb_fast<4, 3>), gr, bl, lds, s, power, n_active, cf, i_max, i_all,
@@ -1025,10 +1206,35 @@ int comb_run(const float* power, int32_t n_active, const int32_t* n_dev, const d
         DDHF_LAUNCH_CHECK();
         return DDHF_OK;
     }
+    const CombArgs& ca = cs.ca;
     const size_t lds = comb_lds_bytes(ca);
     if (lds > 64 * 1024) return DDHF_EINVAL;
     hipLaunchKernelGGL(k_comb, dim3((unsigned)n_active), dim3(kCombThreads), lds, s, power,
                        n_active, ca, sf, snr_best, bin_best, snr_all, n_dev);
+    DDHF_LAUNCH_CHECK();
+    return DDHF_OK;
+}
+
+int ndft_comb_run(const int32_t* row_ptr, const uint32_t* t_rel, const float* a,
+                  const int32_t* active, int32_t n_active, const ddhf_grid_t* grid,
+                  const ddhf_params_t* prm, float* sf, float* snr_best, int32_t* bin_best,
+                  hipStream_t s) {
+    if (!grid_ok(grid) || !comb_params_ok(grid, prm) || n_active < 0) return DDHF_EINVAL;
+    const CombSetup cs = comb_setup(grid, prm);
+    if (!cs.fast) return DDHF_EINVAL;
+    if (n_active == 0) return DDHF_OK;
+    if (!row_ptr || !t_rel || !a || !active || !sf || !snr_best || !bin_best) return DDHF_EINVAL;
+    const GridDev g = grid_dev(grid);
+    const dim3 gr((unsigned)n_active), bl(kFT);
+    if (cs.ca.M == 4 && cs.ca.dk == 3)
+        hipLaunchKernelGGL((k_ndft_comb<4, 3>), gr, bl, cs.lds, s, row_ptr, t_rel, a, active,
+                           n_active, g, cs.ca, cs.i_max, cs.i_all, sf, snr_best, bin_best);
+    else if (cs.ca.M == 5 && cs.ca.dk == 3)
+        hipLaunchKernelGGL((k_ndft_comb<5, 3>), gr, bl, cs.lds, s, row_ptr, t_rel, a, active,
+                           n_active, g, cs.ca, cs.i_max, cs.i_all, sf, snr_best, bin_best);
+    else
+        hipLaunchKernelGGL((k_ndft_comb<-1, -1>), gr, bl, cs.lds, s, row_ptr, t_rel, a, active,
+                           n_active, g, cs.ca, cs.i_max, cs.i_all, sf, snr_best, bin_best);
     DDHF_LAUNCH_CHECK();
     return DDHF_OK;
 }
@@ -1039,4 +1245,12 @@ extern "C" int ddhf_comb_score(const float* power, int32_t n_active, const ddhf_
                                int32_t* bin_best, float* snr_all, void* stream) {
     return comb_run(power, n_active, nullptr, grid, prm, sf, snr_best, bin_best, snr_all,
                     as_stream(stream));
+}
+
+extern "C" int ddhf_ndft_comb(const int32_t* row_ptr, const uint32_t* t_rel, const float* a,
+                              const int32_t* active, int32_t n_active, const ddhf_grid_t* grid,
+                              const ddhf_params_t* prm, float* sf, float* snr_best,
+                              int32_t* bin_best, void* stream) {
+    return ndft_comb_run(row_ptr, t_rel, a, active, n_active, grid, prm, sf, snr_best, bin_best,
+                         as_stream(stream));
 }

@@ -192,6 +192,14 @@ def ddhf_comb_score(power, n_active, grid: Grid, prm: Params, sf, snr_best, bin_
     _check(rc, "ddhf_comb_score")
 
 
+def ddhf_ndft_comb(row_ptr, t_rel, a, active, n_active, grid: Grid, prm: Params, sf, snr_best,
+                   bin_best, stream=None):
+    rc = lib().ddhf_ndft_comb(_p(row_ptr), _p(t_rel), _p(a), _p(active), C.c_int32(n_active),
+                              C.byref(grid), C.byref(prm), _p(sf), _p(snr_best), _p(bin_best),
+                              _stream(stream))
+    _check(rc, "ddhf_ndft_comb")
+
+
 def ddhf_detect_workspace_size(W, H) -> int:
     b = C.c_size_t(0)
     _check(lib().ddhf_detect_workspace_size(C.c_int32(W), C.c_int32(H), C.byref(b)),
@@ -241,7 +249,7 @@ class Window:
 
     def __init__(self, x, y, p, t, W, H, t0, T_w, grid, params, w=None, device="cuda",
                  time_sorted=True, launch: Optional[Launch] = None, order_by_cost=False,
-                 max_boxes=256, capacity: Optional[int] = None):
+                 max_boxes=256, capacity: Optional[int] = None, fused=False):
         import numpy as np
 
         dev = torch.device(device)
@@ -252,6 +260,9 @@ class Window:
         self.grid = make_grid(grid)
         self.prm = make_params(params)
         self.launch = launch
+        # fused: spectrum, flatness and comb in one kernel (ddhf_ndft_comb); no
+        # spectra are kept
+        self.fused = bool(fused)
         self.order_by_cost = int(order_by_cost)
         self.flags = DDHF_INDEX_TIME_SORTED if time_sorted else 0
         cap = max(self.capacity, 1)
@@ -280,6 +291,7 @@ class Window:
         self.boxes = torch.empty(max(self.max_boxes, 1) * 32, dtype=torch.uint8, device=dev)
         self.n_boxes = torch.zeros(2, dtype=torch.int32, device=dev)
         self.power = None
+        self.sf = None
         self.n_active = None
 
     def _load(self, x, y, p, t, w=None):
@@ -321,11 +333,14 @@ class Window:
     def alloc_spectra(self, n_active: Optional[int] = None):
         na = self.n_active if n_active is None else n_active
         K = int(self.grid.K)
-        if self.power is None or self.power.numel() < max(na, 1) * K:
-            self.power = torch.empty(max(na, 1) * K, dtype=torch.float32, device=self.dev)
+        if getattr(self, "sf", None) is None or self.sf.numel() < max(na, 1):
             self.sf = torch.empty(max(na, 1), dtype=torch.float32, device=self.dev)
             self.snr = torch.empty(max(na, 1), dtype=torch.float32, device=self.dev)
             self.bin = torch.empty(max(na, 1), dtype=torch.int32, device=self.dev)
+        if self.fused:
+            return
+        if self.power is None or self.power.numel() < max(na, 1) * K:
+            self.power = torch.empty(max(na, 1) * K, dtype=torch.float32, device=self.dev)
             self.ws_ndft = workspace(ddhf_ndft_workspace_size(max(na, 1), self.n, self.grid,
                                                               self.launch), self.dev)
 
@@ -347,6 +362,16 @@ class Window:
         ddhf_comb_score(self.power, self.n_active, self.grid, self.prm, self.sf, self.snr,
                         self.bin, snr_all, stream)
 
+    def spectra_and_score(self, stream=None):
+        """Flatness and comb scores of every active pixel: the fused kernel, or
+        the spectra to HBM and the comb over them."""
+        if self.fused:
+            ddhf_ndft_comb(self.row_ptr, self.t_rel, self.a, self.active, self.n_active,
+                           self.grid, self.prm, self.sf, self.snr, self.bin, stream)
+        else:
+            self.spectra(stream)
+            self.score(stream)
+
     def detect(self, stream=None):
         ddhf_detect(self.active, self.row_ptr, self.sf, self.snr, self.bin, self.n_active, self.W,
                     self.H, self.grid, self.prm, self.mask, self.labels, self.boxes,
@@ -357,8 +382,7 @@ class Window:
         self.index(stream)
         self.fetch_n_active()
         self.alloc_spectra()
-        self.spectra(stream)
-        self.score(stream)
+        self.spectra_and_score(stream)
         self.detect(stream)
         nb = self.n_boxes.cpu()
         n = min(int(nb[0]), self.max_boxes)

@@ -76,3 +76,29 @@ def test_detect_noalloc_refuses_oversized_frames_on_the_host(lib):
     assert rc == 2
     assert lib.ddhf_detect_noalloc(None, None, None, None, None, 0, 0, 4, C.byref(g), None,
                                    None, None, None, 0, None, None) == 1
+
+
+def test_fused_call_validates_on_the_host(lib):
+    """ddhf_ndft_comb refuses grids beyond the fused kernel's reach before any
+    device call, and zero active pixels need no pointers."""
+    class Grid(C.Structure):
+        _fields_ = [("f0", C.c_int64), ("df", C.c_int64), ("K", C.c_int32), ("mode", C.c_int32),
+                    ("T_w_us", C.c_int64)]
+
+    class Params(C.Structure):
+        _fields_ = [("tau_sf", C.c_float), ("tau_comb", C.c_float), ("alpha", C.c_float),
+                    ("eps_rel", C.c_float), ("M", C.c_int32), ("dk", C.c_int32),
+                    ("h_min", C.c_int32), ("n_min", C.c_int32), ("a_min", C.c_int32),
+                    ("reserved", C.c_int32)]
+    prm = Params(0.89, 1.5, 19.05, 1e-6, 4, 3, 4, 6, 147, 0)
+    ok = Grid(10_000, 1000, 3991, 0, 0)
+    assert lib.ddhf_ndft_comb(None, None, None, None, 0, C.byref(ok), C.byref(prm), None, None,
+                              None, None) == 0
+    too_long = Grid(10_000, 1000, 4097, 0, 0)
+    assert lib.ddhf_ndft_comb(None, None, None, None, 0, C.byref(too_long), C.byref(prm), None,
+                              None, None, None) == 1
+    wide = Params(0.89, 1.5, 19.05, 1e-6, 32, 16, 1, 6, 147, 0)  # band of 1585 ranks
+    assert lib.ddhf_ndft_comb(None, None, None, None, 0, C.byref(ok), C.byref(wide), None, None,
+                              None, None) == 1
+    assert lib.ddhf_ndft_comb(None, None, None, None, 5, C.byref(ok), C.byref(prm), None, None,
+                              None, None) == 1
