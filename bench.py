@@ -30,6 +30,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 FP32_PEAK_TFLOPS = 157.3       # MI355X FP32 vector and FP32 matrix (dense), published
+FP16_PEAK_TFLOPS = 2500.0      # MI355X FP16 matrix (dense), published
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, published
 FLOP_PER_EVENT_BIN = 8         # one complex multiply-accumulate per event and bin
 SOFT_FLOP_PER_EVENT_HARMONIC = 16  # forward complex MAC (8) + backward Re/Im of conj(F) z (8)
@@ -50,7 +51,7 @@ def parse():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="large_1280x720", choices=sorted(WORKLOADS))
-    ap.add_argument("--kernel", default="auto", choices=["auto", "valu", "mfma"])
+    ap.add_argument("--kernel", default="auto", choices=["auto", "valu", "mfma", "mfma16"])
     ap.add_argument("--bpl", type=int, default=64)
     ap.add_argument("--split", type=int, default=0, help="split pixels with more events")
     ap.add_argument("--persistent", type=int, default=0)
@@ -120,10 +121,15 @@ def _pmc_mean_kib(path, counter, name_part):
 TRAFFIC_SOURCES = {"ndft": ["ndft.hip", "ddhf_internal.h"], "comb": ["comb.hip", "ddhf_internal.h"]}
 
 
+KERNEL_NAMES = {0: "valu", 1: "mfma", 2: "mfma16"}
+
+
 def ndft_tag(kernel, bpl):
     """Record tag and rocprofv3 kernel-name fragment of one NDFT instantiation."""
     if kernel == "mfma":
         return f"ndft_mfma{bpl}", f"k_ndft_mfma<{bpl // 16}, 0>"
+    if kernel == "mfma16":
+        return f"ndft_mfma16_{bpl}", f"k_ndft_mfma16<{bpl // 16}, 0>"
     return f"ndft_valu{bpl}", f"k_ndft_valu<{bpl}, 0>"
 
 
@@ -131,8 +137,8 @@ def traffic_summary(args, fetch_csv, write_csv, cal_fetch_csv, cal_write_csv):
     """HBM bytes per launch of the NDFT kernel and of the comb kernel: FETCH_SIZE
     and WRITE_SIZE (KiB per dispatch), each scaled by bytes / reading of the
     plain copy kernel."""
-    if args.kernel not in ("valu", "mfma"):
-        raise SystemExit("--traffic-summary needs --kernel valu or mfma")
+    if args.kernel not in ("valu", "mfma", "mfma16"):
+        raise SystemExit("--traffic-summary needs --kernel valu, mfma or mfma16")
     cf, _ = _pmc_mean_kib(cal_fetch_csv, "FETCH_SIZE", "copyBuffer")
     cw, _ = _pmc_mean_kib(cal_write_csv, "WRITE_SIZE", "copyBuffer")
     fetch_scale = COPY_BYTES / (cf * 1024.0)
@@ -531,7 +537,8 @@ def main():
     if args.kernel == "auto":
         launch = None
     else:
-        kernel = D.DDHF_KERNEL_VALU if args.kernel == "valu" else D.DDHF_KERNEL_MFMA
+        kernel = {"valu": D.DDHF_KERNEL_VALU, "mfma": D.DDHF_KERNEL_MFMA,
+                  "mfma16": D.DDHF_KERNEL_MFMA16}[args.kernel]
         launch = D.make_launch(kernel, args.bpl, split_events=args.split,
                                persistent=args.persistent, nufft_min_events=args.nufft)
     g = D.window_from_synth(win, device="cuda:0", launch=launch,
@@ -596,16 +603,19 @@ def main():
     ndft_ms = float(np.mean(stage_ms["ndft"]))
     flops = FLOP_PER_EVENT_BIN * ev_bins
     achieved_tflops = flops / (ndft_ms * 1e-3) / 1e12
-    kname = "valu" if launch.kernel == D.DDHF_KERNEL_VALU else "mfma"
+    kname = KERNEL_NAMES[int(launch.kernel)]
     tag, kfrag = ndft_tag(kname, launch.bins_per_lane)
     nufft = int(launch.nufft_min_events)
     traffic = (load_traffic(f"{tag}_{args.workload}", kernel_source_digest(TRAFFIC_SOURCES["ndft"]))
                if launch.split_events == 0 and launch.persistent == 0 and nufft == 0 else None)
+    # the split-FP16 contraction is priced against the FP16 matrix peak (its own
+    # dtype); it executes three FP16 products per FP32 term
+    peak = FP16_PEAK_TFLOPS if kname == "mfma16" else FP32_PEAK_TFLOPS
     roof_ndft = {"bound": "alu" if kname == "valu" else "mfma",
                  "kernel": kfrag + (f" + k_nufft (pixels with >= {nufft} events)" if nufft else ""),
                  "achieved": achieved_tflops,
-                 "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
-                 "frac": achieved_tflops / FP32_PEAK_TFLOPS, "traffic": traffic,
+                 "peak": peak, "unit": "TFLOP/s",
+                 "frac": achieved_tflops / peak, "traffic": traffic,
                  "ms": ndft_ms, "algorithmic": f"{FLOP_PER_EVENT_BIN} FLOP x {ev_bins} event-bins"}
     comb_ms = float(np.mean(stage_ms["comb"]))
     comb_bytes = na * K * 4 + na * 12          # read P once; write sf, snr, bin

@@ -113,7 +113,13 @@ typedef struct {
  *   kernel:        0 = VALU (lanes own bins, phasor recurrence per lane),
  *                  1 = MFMA (factorised: F[J b + s] = sum_e U[b,e] V[e,s]
  *                      as FP32 matrix-core products, J = 32);
- *   bins_per_lane: VALU bins per lane per tile (8, 16, 32 or 64);
+ *                  2 = MFMA16 (the same product on the FP16 matrix cores: each
+ *                      operand split into two FP16 parts, three FP16 products
+ *                      with FP32 accumulation, amplitudes scaled by a power
+ *                      of two per unit; same error bound);
+ *   bins_per_lane: VALU bins per lane per tile (8, 16, 32 or 64); MFMA and
+ *                  MFMA16: 16, 32 or 64 (1, 2 or 4 tiles of 1024 bins per
+ *                  wavefront);
  *   split_events:  pixels with more events than this are split into event
  *                  chunks whose partial spectra are summed in a fixed order
  *                  (0 = never split);
@@ -132,7 +138,7 @@ typedef struct {
  *                  correction.  Approximate: same error bound as the direct
  *                  sum (below).  Needs the plain form and K <= 4096.
  * ddhf_autotune fills this struct. */
-enum { DDHF_KERNEL_VALU = 0, DDHF_KERNEL_MFMA = 1 };
+enum { DDHF_KERNEL_VALU = 0, DDHF_KERNEL_MFMA = 1, DDHF_KERNEL_MFMA16 = 2 };
 typedef struct {
     int32_t kernel;
     int32_t bins_per_lane;

@@ -24,9 +24,15 @@ static const ddhf_launch_t kCandidates[] = {
     {DDHF_KERNEL_MFMA, 64, 512, 0, 0, 0},  {DDHF_KERNEL_MFMA, 32, 1024, 1, 0, 0},
     {DDHF_KERNEL_VALU, 32, 0, 0, 0, 0},    {DDHF_KERNEL_VALU, 64, 0, 0, 0, 0},
     {DDHF_KERNEL_VALU, 32, 256, 1, 0, 0},
+    // split-FP16 matrix-core products
+    {DDHF_KERNEL_MFMA16, 64, 0, 0, 0, 0},   {DDHF_KERNEL_MFMA16, 32, 0, 0, 0, 0},
+    {DDHF_KERNEL_MFMA16, 64, 0, 1, 0, 0},   {DDHF_KERNEL_MFMA16, 64, 512, 1, 0, 0},
+    {DDHF_KERNEL_MFMA16, 64, 512, 0, 0, 0}, {DDHF_KERNEL_MFMA16, 64, 2048, 1, 0, 0},
     // heavy pixels through the NUFFT path, direct sum for the rest
     {DDHF_KERNEL_MFMA, 64, 0, 0, 0, 512},  {DDHF_KERNEL_MFMA, 64, 0, 0, 0, 256},
     {DDHF_KERNEL_MFMA, 64, 0, 0, 0, 128},  {DDHF_KERNEL_MFMA, 64, 0, 0, 0, 64},
+    {DDHF_KERNEL_MFMA16, 64, 0, 0, 0, 2048}, {DDHF_KERNEL_MFMA16, 64, 0, 0, 0, 1024},
+    {DDHF_KERNEL_MFMA16, 64, 0, 0, 0, 512},  {DDHF_KERNEL_MFMA16, 64, 0, 0, 0, 256},
 };
 static const int kNumCandidates = (int)(sizeof(kCandidates) / sizeof(kCandidates[0]));
 

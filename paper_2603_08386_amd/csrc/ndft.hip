@@ -162,10 +162,12 @@ __device__ __forceinline__ void load_event(int lane, int32_t c0, int32_t end,
 // Stages events [c0, c0 + 64) of a unit from the lanes' loaded (t, a): exact
 // residues A = f_tile t mod Q and D = df t mod Q as fixed-point fractions,
 // and the step phasor exp(i 2 pi step_mul D / Q) from the 48-bit fraction of D.
+template <bool ZERO_TAIL = false>
 __device__ __forceinline__ void stage_loaded(EvStage* st, int lane, int32_t c0, int32_t end,
                                              uint32_t t_lane, float a_lane, uint64_t f_tile,
                                              const GridDev& g, uint32_t step_mul) {
     const int32_t e = c0 + lane;
+    if (ZERO_TAIL && e >= end) st[lane] = EvStage{0u, 0u, 0u, 0u, 0.0f, 1.0f, 0.0f, 0.0f};
     if (e < end) {
         const uint64_t t = t_lane;
         EvStage s;
@@ -291,6 +293,68 @@ __device__ __forceinline__ MfOps mf_operands(const EvStage& s, bool upper, uint3
 
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 
+// Writes a unit's MFMA accumulators: the power (rescaled by 2^(2 ex)) into the
+// spectrum row, or the complex partial sums (rescaled by 2^ex) into the unit's
+// workspace slot.  Register r of tile b holds row b*32 + 8 (r / 4) + 4 half +
+// r % 4, column lane mod 32, so every store is a compile-time offset from one
+// per-lane base.
+template <int NB>
+__device__ __forceinline__ void store_unit(const f32x16* cre, const f32x16* cim, const Unit& un,
+                                           int tile_base, int lane, int K, int ex,
+                                           float* __restrict__ power, float* partials) {
+    // the lane is passed through an opaque move so that the offsets are formed
+    // here, per unit, rather than hoisted out of the unit loop and held in
+    // registers across it
+    int lane_u;
+    asm volatile("v_mov_b32 %0, %1" : "=v"(lane_u) : "v"(lane));
+    const int col = lane_u & 31;
+    const int half = lane_u >> 5;
+    if (un.slot < 0) {
+        // Buffer stores into the row from the tile's first bin: the resource
+        // (scalar registers) spans the row's remaining K - tile_base bins, so
+        // the stores of bins >= K fall outside it and are dropped by the
+        // hardware's range check on the per-lane byte offset (the whole offset
+        // is in the lane's register: no scalar or instruction offset).
+        const int u = __builtin_amdgcn_readfirstlane(un.u);
+        const int tb = __builtin_amdgcn_readfirstlane(tile_base);
+        const int lim0 = K - tb;                     // wave-uniform, > 0
+        const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+            power + ((int64_t)u * K + tb), 0, lim0 * 4, 0x00020000);
+        const uint32_t vb = 4u * (uint32_t)(128 * half + col);
+        auto rows = [&](auto scaled) {
+#pragma unroll
+            for (int b = 0; b < NB; ++b) {
+#pragma unroll
+                for (int r = 0; r < 16; ++r) {
+                    const int R = b * 32 + 8 * (r >> 2) + (r & 3);  // row of the lower half-wave
+                    float v = cre[b][r] * cre[b][r] + cim[b][r] * cim[b][r];
+                    if (decltype(scaled)::value) v = ldexpf(v, 2 * ex);
+                    uint32_t vo;
+                    asm("v_add_u32 %0, %1, %2" : "=v"(vo) : "i"(4 * 32 * R), "v"(vb));
+                    __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v), rs, vo, 0, 0);
+                }
+            }
+        };
+        if (ex == 0) rows(std::false_type());
+        else rows(std::true_type());
+    } else {
+        float2* part = (float2*)partials + (int64_t)un.slot * (NB * 1024) + 128 * half + col;
+#pragma unroll
+        for (int b = 0; b < NB; ++b) {
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                const int R = b * 32 + 8 * (r >> 2) + (r & 3);
+                float vr = cre[b][r], vi = cim[b][r];
+                if (ex != 0) {
+                    vr = ldexpf(vr, ex);
+                    vi = ldexpf(vi, ex);
+                }
+                part[R * 32] = make_float2(vr, vi);
+            }
+        }
+    }
+}
+
 template <int NB, int MODE>
 __global__ __launch_bounds__(64, 2) void k_ndft_mfma(const int32_t* __restrict__ row_ptr,
                                                      const uint32_t* __restrict__ t_rel,
@@ -358,35 +422,161 @@ __global__ __launch_bounds__(64, 2) void k_ndft_mfma(const int32_t* __restrict__
             }
             __syncthreads();
         }
-        // the lane is passed through an opaque move so that the store offsets are
-        // formed here, per unit, rather than hoisted out of the unit loop and
-        // held in registers across it
-        int lane_u;
-        asm volatile("v_mov_b32 %0, %1" : "=v"(lane_u) : "v"(lane));
-        const int col = lane_u & 31;
-        const int half = lane_u >> 5;
-        if (un.slot < 0) {
-            float* out = power + (int64_t)un.u * g.K;
-#pragma unroll
-            for (int b = 0; b < NB; ++b) {
-#pragma unroll
-                for (int r = 0; r < 16; ++r) {
-                    const int row = b * 32 + 8 * (r >> 2) + 4 * half + (r & 3);
-                    const int j = tile_base + row * 32 + col;
-                    if (j < g.K) out[j] = cre[b][r] * cre[b][r] + cim[b][r] * cim[b][r];
-                }
-            }
-        } else {
-            float2* part = (float2*)wk.partials + (int64_t)un.slot * (NB * 1024);
-#pragma unroll
-            for (int b = 0; b < NB; ++b) {
-#pragma unroll
-                for (int r = 0; r < 16; ++r) {
-                    const int row = b * 32 + 8 * (r >> 2) + 4 * half + (r & 3);
-                    part[row * 32 + col] = make_float2(cre[b][r], cim[b][r]);
-                }
-            }
+        store_unit<NB>(cre, cim, un, tile_base, lane, g.K, 0, power, wk.partials);
+        if (MODE == kModeQueue && queue_pending(iter)) {
+            have_nx = next_unit<MODE, true>(wk, row_ptr, active, n_active, n_wtiles, iter, nx);
+            if (have_nx) load_event(lane, nx.beg, nx.end, t_rel, av, t_ld, a_ld);
         }
+        un = nx;
+        have = have_nx;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// MFMA kernel on the FP16 matrix cores with split operands.  The same
+// factorised product, eight events per v_mfma_f32_32x32x16_f16 (k = 2 e + {0:
+// real, 1: imaginary}; lane l holds k = 8 (l / 32) .. + 7, i.e. events
+// 4 (l / 32) .. + 3 of the group, for row / column l mod 32).  Each FP32
+// operand x is split into x_h = fp16(x) (toward zero) and x_l = fp16(x - x_h),
+// and A B = A_h B_h + A_l B_h + A_h B_l up to |A_l B_l| ~ 2^-20 |A B|: three
+// FP16 products with FP32 accumulation give FP32-like terms at 3/16 of the
+// FP32 matrix-core time.  The events' amplitudes are scaled by a power of two,
+// 2^-e with max |a| 2^-e in (1/2, 1] over the unit, so that no operand leaves
+// the FP16 range; the spectrum is scaled back exactly.  Tile b's U rows are
+// tile 0's rotated b times by exp(i 2 pi 1024 D / Q).
+// ---------------------------------------------------------------------------
+typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+
+// x - (float)h.lo and x - (float)h.hi for a packed FP16 pair h, one mixed-precision
+// FMA each (exact here: h holds x rounded toward zero)
+__device__ __forceinline__ float sub_f16lo(float x, uint32_t h) {
+    float d;
+    asm("v_fma_mix_f32 %0, %1, 1.0, -%2 op_sel_hi:[0,0,1]" : "=v"(d) : "v"(x), "v"(h));
+    return d;
+}
+__device__ __forceinline__ float sub_f16hi(float x, uint32_t h) {
+    float d;
+    asm("v_fma_mix_f32 %0, %1, 1.0, -%2 op_sel:[0,0,1] op_sel_hi:[0,0,1]" : "=v"(d) : "v"(x), "v"(h));
+    return d;
+}
+
+// (fp16(x), fp16(y)) toward zero and the packed remainders (fp16(x - x_h), fp16(y - y_h))
+__device__ __forceinline__ void split_pk(float x, float y, uint32_t& hi, uint32_t& lo) {
+    hi = __builtin_bit_cast(uint32_t, __builtin_amdgcn_cvt_pkrtz(x, y));
+    lo = __builtin_bit_cast(uint32_t,
+                            __builtin_amdgcn_cvt_pkrtz(sub_f16lo(x, hi), sub_f16hi(y, hi)));
+}
+
+__device__ __forceinline__ f16x8 as_f16x8(const u32x4& v) { return __builtin_bit_cast(f16x8, v); }
+
+// wavefronts per SIMD the register budget is set for: 128 accumulator
+// registers at four tiles leave room for two, 64 at two tiles for three
+constexpr int f16_min_waves(int nb) { return nb == 4 ? 2 : (nb == 2 ? 3 : 6); }
+
+template <int NB, int MODE>
+__global__ __launch_bounds__(64, f16_min_waves(NB)) void k_ndft_mfma16(const int32_t* __restrict__ row_ptr,
+                                                       const uint32_t* __restrict__ t_rel,
+                                                       const float* __restrict__ av,
+                                                       const int32_t* __restrict__ active,
+                                                       int32_t n_active, GridDev g, int n_wtiles,
+                                                       float* __restrict__ power, WorkDev wk) {
+    static_assert(NB == 1 || NB == 2 || NB == 4, "MFMA tiles per wave");
+    __shared__ EvStage st[64];
+    const int lane = threadIdx.x;
+    const uint32_t r32 = (uint32_t)(lane & 31);
+    const int kb = lane >> 5;  // which four events of a group of eight
+    int64_t iter = 0;
+    Unit un;
+    bool have = next_unit<MODE>(wk, row_ptr, active, n_active, n_wtiles, iter, un);
+    uint32_t t_ld = 0u;
+    float a_ld = 0.0f;
+    if (have) load_event(lane, un.beg, un.end, t_rel, av, t_ld, a_ld);
+    while (have) {
+        Unit nx;
+        bool have_nx = next_unit<MODE, true>(wk, row_ptr, active, n_active, n_wtiles, iter, nx);
+        const int tile_base = un.wt * NB * 1024;
+        const uint64_t f_tile = (uint64_t)(g.f0 + (int64_t)tile_base * g.df);
+        // unit amplitude scale 2^-ex (the first chunk is already in registers)
+        float amax = fabsf(a_ld);
+        for (int32_t c = un.beg + 64; c < un.end; c += 64) {
+            const int32_t e = c + lane;
+            if (e < un.end) amax = fmaxf(amax, fabsf(av[e]));
+        }
+        amax = wave_max(amax);
+        // ex = ceil(log2 max|a|): amplitudes of +-1 need no scaling
+        int ex = 0;
+        if (amax > 0.0f) {
+            const float m = frexpf(amax, &ex);  // amax = m 2^ex, m in [1/2, 1)
+            if (m == 0.5f) --ex;
+        }
+        ex = __builtin_amdgcn_readfirstlane(ex);
+        const float sc = ldexpf(1.0f, -ex);
+        f32x16 cre[NB], cim[NB];
+#pragma unroll
+        for (int b = 0; b < NB; ++b) {
+#pragma unroll
+            for (int r = 0; r < 16; ++r) { cre[b][r] = 0.0f; cim[b][r] = 0.0f; }
+        }
+        if (un.beg >= un.end && have_nx) load_event(lane, nx.beg, nx.end, t_rel, av, t_ld, a_ld);
+        for (int32_t c0 = un.beg; c0 < un.end; c0 += 64) {
+            stage_loaded<true>(st, lane, c0, un.end, t_ld, a_ld * sc, f_tile, g, 1024u);
+            __syncthreads();
+            if (c0 + 64 < un.end) load_event(lane, c0 + 64, un.end, t_rel, av, t_ld, a_ld);
+            else if (have_nx) load_event(lane, nx.beg, nx.end, t_rel, av, t_ld, a_ld);
+            const int ne = (un.end - c0) < 64 ? (un.end - c0) : 64;
+            for (int k0 = 0; k0 < ne; k0 += 8) {
+                u32x4 brh, brl, bih, bil;
+                float ur[4], ui[4], rc[4], rs[4];
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const EvStage sv = st[k0 + 4 * kb + q];
+                    float vs, vc, sn, cs;
+                    // column phase s D; row phase A + 32 s D from it (the factor 32
+                    // scales its 2^-32 truncation to 2^-27 revolutions)
+                    const uint32_t phv = frac_phase(0u, sv.q1lo, sv.q1hi, sv.q2, r32);
+                    sincos_rev(phv, vs, vc);
+                    sincos_rev(sv.phiA + (phv << 5), sn, cs);
+                    // B (real part): (Re V, -Im V); B (imaginary part): (Im V, Re V)
+                    const uint32_t h = __builtin_bit_cast(uint32_t, __builtin_amdgcn_cvt_pkrtz(vc, -vs));
+                    const float dr = sub_f16lo(vc, h), di = sub_f16hi(-vs, h);
+                    brh[q] = h;
+                    brl[q] = __builtin_bit_cast(uint32_t, __builtin_amdgcn_cvt_pkrtz(dr, di));
+                    bih[q] = __builtin_bit_cast(uint32_t, __builtin_amdgcn_cvt_pkrtz(vs, vc));
+                    bil[q] = __builtin_bit_cast(uint32_t, __builtin_amdgcn_cvt_pkrtz(-di, dr));
+                    ur[q] = cs * sv.a;
+                    ui[q] = sn * sv.a;
+                    rc[q] = sv.wc;
+                    rs[q] = sv.ws;
+                }
+#pragma unroll
+                for (int b = 0; b < NB; ++b) {
+                    u32x4 ah, al;
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) {
+                        if (b > 0) {
+                            const float xr = ur[q] * rc[q] - ui[q] * rs[q];
+                            const float xi = ur[q] * rs[q] + ui[q] * rc[q];
+                            ur[q] = xr;
+                            ui[q] = xi;
+                        }
+                        uint32_t hq, lq;
+                        split_pk(ur[q], ui[q], hq, lq);
+                        ah[q] = hq;
+                        al[q] = lq;
+                    }
+                    const f16x8 Ah = as_f16x8(ah), Al = as_f16x8(al);
+                    cre[b] = __builtin_amdgcn_mfma_f32_32x32x16_f16(Ah, as_f16x8(brh), cre[b], 0, 0, 0);
+                    cim[b] = __builtin_amdgcn_mfma_f32_32x32x16_f16(Ah, as_f16x8(bih), cim[b], 0, 0, 0);
+                    cre[b] = __builtin_amdgcn_mfma_f32_32x32x16_f16(Al, as_f16x8(brh), cre[b], 0, 0, 0);
+                    cim[b] = __builtin_amdgcn_mfma_f32_32x32x16_f16(Al, as_f16x8(bih), cim[b], 0, 0, 0);
+                    cre[b] = __builtin_amdgcn_mfma_f32_32x32x16_f16(Ah, as_f16x8(brl), cre[b], 0, 0, 0);
+                    cim[b] = __builtin_amdgcn_mfma_f32_32x32x16_f16(Ah, as_f16x8(bil), cim[b], 0, 0, 0);
+                }
+            }
+            __syncthreads();
+        }
+        store_unit<NB>(cre, cim, un, tile_base, lane, g.K, ex, power, wk.partials);
         if (MODE == kModeQueue && queue_pending(iter)) {
             have_nx = next_unit<MODE, true>(wk, row_ptr, active, n_active, n_wtiles, iter, nx);
             if (have_nx) load_event(lane, nx.beg, nx.end, t_rel, av, t_ld, a_ld);
@@ -755,7 +945,7 @@ static bool make_plan(const ddhf_launch_t* launch, int32_t n_active, int64_t n_e
         if (p->bpl != 8 && p->bpl != 16 && p->bpl != 32 && p->bpl != 64) return false;
         p->nb = 0;
         p->tile_bins = 64 * p->bpl;
-    } else if (p->kernel == DDHF_KERNEL_MFMA) {
+    } else if (p->kernel == DDHF_KERNEL_MFMA || p->kernel == DDHF_KERNEL_MFMA16) {
         if (p->bpl != 16 && p->bpl != 32 && p->bpl != 64) return false;
         p->nb = p->bpl / 16;
         p->tile_bins = p->nb * 1024;
@@ -952,6 +1142,11 @@ extern "C" int ddhf_ndft_workspace_size(int32_t n_active, int64_t n_events,
         return run_plan(p, w, k_ndft_mfma<NB, kModePlain>, k_ndft_mfma<NB, kModeList>,          \
                         k_ndft_mfma<NB, kModeQueue>, row_ptr, t_rel, a, active, n_active, g,    \
                         power, gw, s, n_dev);
+#define DDHF_MFMA16_CASE(NB)                                                                    \
+    case NB:                                                                                    \
+        return run_plan(p, w, k_ndft_mfma16<NB, kModePlain>, k_ndft_mfma16<NB, kModeList>,      \
+                        k_ndft_mfma16<NB, kModeQueue>, row_ptr, t_rel, a, active, n_active, g,  \
+                        power, gw, s, n_dev);
 
 namespace ddhf {
 int ndft_run(const int32_t* row_ptr, const uint32_t* t_rel, const float* a, const int32_t* active,
@@ -974,6 +1169,14 @@ int ndft_run(const int32_t* row_ptr, const uint32_t* t_rel, const float* a, cons
             DDHF_MFMA_CASE(1)
             DDHF_MFMA_CASE(2)
             DDHF_MFMA_CASE(4)
+            default: return DDHF_EINVAL;
+        }
+    }
+    if (p.kernel == DDHF_KERNEL_MFMA16) {
+        switch (p.nb) {
+            DDHF_MFMA16_CASE(1)
+            DDHF_MFMA16_CASE(2)
+            DDHF_MFMA16_CASE(4)
             default: return DDHF_EINVAL;
         }
     }

@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(_HERE, "libddhf.so")
 
 DDHF_OK, DDHF_EINVAL, DDHF_ENOSPACE, DDHF_EHIP, DDHF_ETRUNC = 0, 1, 2, 3, 4
 DDHF_GRID_HZ, DDHF_GRID_MODES = 0, 1
-DDHF_KERNEL_VALU, DDHF_KERNEL_MFMA = 0, 1
+DDHF_KERNEL_VALU, DDHF_KERNEL_MFMA, DDHF_KERNEL_MFMA16 = 0, 1, 2
 DDHF_INDEX_TIME_SORTED = 1
 DDHF_DETECT_MAX_CANDIDATES = 1024
 DDHF_DETECT_NOALLOC_MAX_PIXELS = 1 << 20

@@ -134,7 +134,8 @@ def gpu_power(win, launch=None, params=None):
 
 
 LAUNCHES = [(D.DDHF_KERNEL_VALU, b) for b in (8, 16, 32, 64)] + \
-           [(D.DDHF_KERNEL_MFMA, b) for b in (16, 32, 64)]
+           [(D.DDHF_KERNEL_MFMA, b) for b in (16, 32, 64)] + \
+           [(D.DDHF_KERNEL_MFMA16, b) for b in (16, 32, 64)]
 
 
 @pytest.mark.parametrize("kernel,bpl", LAUNCHES)
@@ -150,7 +151,7 @@ def test_ndft_tiny_full(kernel, bpl):
     assert err <= TOL_P
 
 
-@pytest.mark.parametrize("kernel,bpl", [(0, 32), (1, 64), (1, 16)])
+@pytest.mark.parametrize("kernel,bpl", [(0, 32), (1, 64), (1, 16), (2, 64), (2, 16)])
 def test_ndft_mode_grid_and_ragged_bins(kernel, bpl):
     """Mode grid (integer modes over the window) with K not a multiple of
     any tile, T_w = 33,333 us (30 FPS windows)."""
@@ -163,7 +164,8 @@ def test_ndft_mode_grid_and_ragged_bins(kernel, bpl):
     assert power_err(P, P64, r["row_ptr"], r["active"], r["a"]) <= TOL_P
 
 
-def test_ndft_closed_forms_on_gpu():
+@pytest.mark.parametrize("kernel,bpl", [(0, 32), (1, 64), (2, 64)])
+def test_ndft_closed_forms_on_gpu(kernel, bpl):
     """Coincident events give a flat (sum a)^2 spectrum; a strictly periodic
     train gives C^2 at its harmonics."""
     W, H, T_w = 4, 1, 50_000
@@ -177,14 +179,14 @@ def test_ndft_closed_forms_on_gpu():
     grid = Grid(f0=1000, df=1000, K=2000)
     win = synth.Window(W, H, synth.T0_US, T_w, x[o], np.zeros(22, np.uint16), p[o], t[o], grid,
                        Params(n_min=1), np.zeros((1, 4), bool), {})
-    banner("ndft closed forms")
-    g, P = gpu_power(win)
+    banner(f"ndft closed forms kernel={kernel} bpl={bpl}")
+    g, P = gpu_power(win, D.make_launch(kernel, bpl))
     assert np.allclose(P[0], 144.0, rtol=1e-5)
     for n in range(1, 8):
         assert P[1][250 * n - 1] == pytest.approx(100.0, rel=1e-4)
 
 
-@pytest.mark.parametrize("kernel,bpl", [(0, 32), (1, 64), (1, 32)])
+@pytest.mark.parametrize("kernel,bpl", [(0, 32), (1, 64), (1, 32), (2, 64), (2, 32)])
 def test_ndft_medium_sampled(kernel, bpl):
     win = synth.medium_window(2)
     banner(f"ndft medium n={win.n} kernel={kernel} bpl={bpl}")
@@ -200,7 +202,7 @@ def test_ndft_medium_sampled(kernel, bpl):
     assert err <= TOL_P
 
 
-@pytest.mark.parametrize("kernel,bpl", [(0, 32), (1, 64)])
+@pytest.mark.parametrize("kernel,bpl", [(0, 32), (1, 64), (2, 64)])
 def test_ndft_deterministic(kernel, bpl):
     win = synth.tiny_window(3)
     _, P1 = gpu_power(win, D.make_launch(kernel, bpl))
@@ -217,6 +219,33 @@ def test_ndft_empty_and_degenerate():
     win = synth.random_window(31, 1, 1, 1000, 1, grid, params=Params(n_min=1))
     g, P = gpu_power(win)
     assert np.allclose(P, 1.0, rtol=1e-6)
+
+
+@pytest.mark.parametrize("kernel,bpl,split", [(1, 64, 0), (2, 64, 0), (2, 32, 40), (2, 16, 0)])
+def test_ndft_weighted_events(kernel, bpl, split):
+    """Per-event weights over twelve decades (the split-FP16 kernel scales each
+    unit's amplitudes by a power of two): power within the bound against the
+    oracle, including pixels cut into chunks."""
+    rng = np.random.default_rng(11)
+    grid = Grid(f0=2000, df=1000, K=1500)
+    base = synth.random_window(12, 6, 4, 20_000, 3000, grid, params=Params(n_min=1))
+    w = (10.0 ** rng.uniform(-6, 6, size=base.n)).astype(np.float32)
+    w[rng.random(base.n) < 0.1] = 0.0
+    banner(f"ndft weighted kernel={kernel} bpl={bpl} split={split}")
+    g = D.Window(base.x, base.y, base.p, base.t, base.W, base.H, base.t0, base.T_w, grid,
+                 base.params, w=w, device=DEV, launch=D.make_launch(kernel, bpl, split))
+    g.index()
+    g.fetch_n_active()
+    g.alloc_spectra()
+    g.spectra()
+    torch.cuda.synchronize()
+    P = to_np(g.power, g.n_active * grid.K).reshape(g.n_active, grid.K)
+    r = oracle.build_pixel_index(base.x, base.y, base.p, base.t, base.W, base.H, base.t0,
+                                 base.T_w, w=w)
+    act = oracle.active_pixels(r["row_ptr"], 1)
+    assert np.array_equal(to_np(g.active, g.n_active), act)
+    P64 = oracle.ndft_power(r["row_ptr"], r["t_rel"], r["a"], act, grid)
+    assert power_err(P, P64, r["row_ptr"], act, r["a"]) <= TOL_P
 
 
 # ---------------------------------------------------------------------------
@@ -539,6 +568,9 @@ FORMS = [
     (1, 64, 128, 1, True),
     (1, 32, 50, 0, False),
     (1, 16, 300, 1, True),
+    (2, 64, 128, 1, True),
+    (2, 32, 50, 0, False),
+    (2, 16, 0, 1, False),
 ]
 
 
@@ -697,14 +729,15 @@ def test_ndft_nufft_medium_and_mode_grid():
     assert err <= TOL_P
 
 
-def test_bench_launch_large_sampled():
-    """The launch bench.py times (MFMA, 4096 bins per wavefront, plain,
-    cost-ordered) on the 1280x720 window it times: sampled rows of the power
-    against the oracle, and the comb of those rows against the oracle's comb on
-    the same FP32 spectra."""
+@pytest.mark.parametrize("kernel", [D.DDHF_KERNEL_MFMA16, D.DDHF_KERNEL_MFMA])
+def test_bench_launch_large_sampled(kernel):
+    """The launches bench.py times (split-FP16 or FP32 matrix cores, 4096 bins
+    per wavefront, plain, cost-ordered) on the 1280x720 window it times: sampled
+    rows of the power against the oracle, and the comb of those rows against the
+    oracle's comb on the same FP32 spectra."""
     win = synth.large_window()
-    banner(f"bench launch large n={win.n}")
-    g, P, act = gpu_power_form(win, 1, 64, 0, 0, True)
+    banner(f"bench launch large n={win.n} kernel={kernel}")
+    g, P, act = gpu_power_form(win, kernel, 64, 0, 0, True)
     g.score()
     torch.cuda.synchronize()
     na = g.n_active
