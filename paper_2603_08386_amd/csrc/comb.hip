@@ -378,12 +378,13 @@ struct Loc {
     uint32_t before;
 };
 
-// Per-segment loops run with compile-time bounds for threads whose 16 bins
-// all lie inside [0, K) (every wave except the one holding bin K - 1), and
-// with a bounds test per bin otherwise.
+// Per-segment loops run with compile-time bounds in wavefronts whose threads'
+// 16 bins all lie inside [0, K) (every wave except the one holding bin K - 1),
+// and with a bounds test per bin otherwise.  The choice is per wavefront, so
+// that the one holding the end of the spectrum runs one path, not both.
 template <class F>
 __device__ __forceinline__ void seg_dispatch(int nmine, F&& f) {
-    if (nmine == kFastItems) f(std::true_type{});
+    if (__builtin_amdgcn_ballot_w64(nmine != kFastItems) == 0ull) f(std::true_type{});
     else f(std::false_type{});
 }
 // bin j of the segment is inside [0, K): always when the segment is full
@@ -875,6 +876,10 @@ __device__ __forceinline__ void comb_fast_pixel(const CombArgs& ca, int32_t u, i
 #pragma unroll
         for (int r = 0; r < kKeep; ++r) {
             const int i = dk + tid + r * kFT;
+            if (dk + r * kFT > i_max) {  // the whole round lies beyond the candidates
+                nv[r] = -1.0f;
+                continue;
+            }
             if (MT > 0 && dk + kFT - 1 + r * kFT <= i_all) {
                 float smax = 0.0f;
 #pragma unroll
@@ -900,7 +905,8 @@ __device__ __forceinline__ void comb_fast_pixel(const CombArgs& ca, int32_t u, i
             }
         };
 #pragma unroll
-        for (int r = 0; r < kKeep; ++r) offer(dk + tid + r * kFT, nv[r]);
+        for (int r = 0; r < kKeep; ++r)
+            if (dk + r * kFT <= i_max) offer(dk + tid + r * kFT, nv[r]);
         for (int i = dk + tid + kKeep * kFT; i <= i_max; i += kFT) offer(i, n_of(i));
         __syncthreads();
         n_eval = (int)s_qn;
