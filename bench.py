@@ -52,6 +52,9 @@ def parse():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="large_1280x720", choices=sorted(WORKLOADS))
     ap.add_argument("--kernel", default="auto", choices=["auto", "valu", "mfma", "mfma16"])
+    ap.add_argument("--scoring", default="auto", choices=["auto", "split", "fused"],
+                    help="spectra to HBM then comb, the fused spectrum + comb kernel, or the "
+                         "faster of the two on this window (ddhf_autotune_scoring)")
     ap.add_argument("--bpl", type=int, default=64)
     ap.add_argument("--split", type=int, default=0, help="split pixels with more events")
     ap.add_argument("--persistent", type=int, default=0)
@@ -557,6 +560,18 @@ def main():
                 "seconds": time.perf_counter() - t0}
         print(f"[bench] autotuned launch {tune}", file=sys.stderr, flush=True)
 
+    scoring = None
+    if args.scoring == "auto":
+        if g.n_active is None:
+            g.index()
+            g.fetch_n_active()
+        g.launch = launch
+        fused, ms_s, ms_f = g.select_scoring()
+        scoring = {"fused": fused, "ms_split": ms_s, "ms_fused": ms_f}
+        print(f"[bench] scoring {scoring}", file=sys.stderr, flush=True)
+    else:
+        g.fused = args.scoring == "fused"
+
     ev = lambda: torch.cuda.Event(enable_timing=True)
     stage_ms = {"index": [], "ndft": [], "comb": [], "detect": []}
     frame_ms = []
@@ -570,9 +585,13 @@ def main():
         na = g.fetch_n_active()
         g.alloc_spectra()
         e1b.record(stream)
-        g.spectra()
-        e2.record(stream)
-        g.score()
+        if g.fused:
+            g.spectra_and_score()  # one kernel: its time is reported under "ndft"
+            e2.record(stream)
+        else:
+            g.spectra()
+            e2.record(stream)
+            g.score()
         e3.record(stream)
         g.detect()
         e4.record(stream)
@@ -618,14 +637,23 @@ def main():
                  "frac": achieved_tflops / peak, "traffic": traffic,
                  "ms": ndft_ms, "algorithmic": f"{FLOP_PER_EVENT_BIN} FLOP x {ev_bins} event-bins"}
     comb_ms = float(np.mean(stage_ms["comb"]))
-    comb_bytes = na * K * 4 + na * 12          # read P once; write sf, snr, bin
-    comb_gbs = comb_bytes / (comb_ms * 1e-3) / 1e9
-    roof_comb = {"bound": "hbm", "kernel": "k_comb_fast", "achieved": comb_gbs,
-                 "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": comb_gbs / HBM_PEAK_GBS,
-                 "traffic": load_traffic(f"comb_fast_{args.workload}",
-                                         kernel_source_digest(TRAFFIC_SOURCES["comb"])),
-                 "ms": comb_ms, "algorithmic": f"{comb_bytes} bytes (P read + per-pixel outputs)"}
-    dominant = roof_ndft if ndft_ms >= comb_ms else roof_comb
+    if g.fused:
+        # one kernel forms and scores the spectra: priced as the FP32 contraction
+        roof_ndft.update({"kernel": "k_ndft_comb (spectrum in LDS, flatness and comb)",
+                          "bound": "mfma", "peak": FP32_PEAK_TFLOPS,
+                          "frac": achieved_tflops / FP32_PEAK_TFLOPS, "traffic": None})
+        roof_comb = None
+        dominant = roof_ndft
+    else:
+        comb_bytes = na * K * 4 + na * 12          # read P once; write sf, snr, bin
+        comb_gbs = comb_bytes / (comb_ms * 1e-3) / 1e9
+        roof_comb = {"bound": "hbm", "kernel": "k_comb_fast", "achieved": comb_gbs,
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": comb_gbs / HBM_PEAK_GBS,
+                     "traffic": load_traffic(f"comb_fast_{args.workload}",
+                                             kernel_source_digest(TRAFFIC_SOURCES["comb"])),
+                     "ms": comb_ms,
+                     "algorithmic": f"{comb_bytes} bytes (P read + per-pixel outputs)"}
+        dominant = roof_ndft if ndft_ms >= comb_ms else roof_comb
 
     out = {
         "metric": "NDFT pixel*bins/s (% FP32 VALU peak) + p50/p99 frame latency, 1280x720",
@@ -645,7 +673,8 @@ def main():
                    "K": K, "grid_mHz": [int(win.grid.f0), int(win.grid.df)],
                    "ndft_kernel": tag, "bins_per_lane": launch.bins_per_lane,
                    "split_events": launch.split_events, "persistent": launch.persistent,
-                   "nufft_min_events": nufft, "cost_order": args.cost_order, "autotune": tune},
+                   "nufft_min_events": nufft, "cost_order": args.cost_order, "autotune": tune,
+                   "scoring": "fused" if g.fused else "split", "scoring_tune": scoring},
         "ndft": {"ms": ndft_ms, "pixel_bins_per_s": na * K / (ndft_ms * 1e-3),
                  "event_bins_per_s": ev_bins / (ndft_ms * 1e-3),
                  "pct_fp32_peak": 100.0 * achieved_tflops / FP32_PEAK_TFLOPS},

@@ -225,6 +225,20 @@ int ddhf_autotune(const int32_t* row_ptr, const uint32_t* t_rel, const float* a,
                   const ddhf_grid_t* grid, float* power, void* ws, size_t ws_bytes,
                   const char* cache_path, ddhf_launch_t* out, float* best_ms, void* stream);
 
+/* Chooses how spectra are scored for this CSR: ddhf_ndft_power with `launch`
+ * (e.g. ddhf_autotune's pick) followed by ddhf_comb_score, or the fused
+ * ddhf_ndft_comb (below).  Times each with HIP events on `stream` (a warm-up
+ * and five runs, best kept; it synchronises) and sets *use_fused = 1 when the
+ * fused call is at least 2 % faster; *ms_split and *ms_fused (nullable) get the
+ * times (-1 for a form the shape does not allow).  power, ws, ws_bytes as for
+ * ddhf_ndft_power; sf, snr_best, bin_best receive the chosen form's scores. */
+int ddhf_autotune_scoring(const int32_t* row_ptr, const uint32_t* t_rel, const float* a,
+                          const int32_t* active, int32_t n_active, int64_t n_events,
+                          const ddhf_grid_t* grid, const ddhf_params_t* prm,
+                          const ddhf_launch_t* launch, float* power, void* ws, size_t ws_bytes,
+                          float* sf, float* snr_best, int32_t* bin_best, int32_t* use_fused,
+                          float* ms_split, float* ms_fused, void* stream);
+
 /* ---- 4. spectral flatness + harmonic comb (Eq. 7-11) --------------------- */
 
 /* For each row u of power [n_active * K]:

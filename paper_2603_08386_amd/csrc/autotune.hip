@@ -171,3 +171,68 @@ extern "C" int ddhf_autotune(const int32_t* row_ptr, const uint32_t* t_rel, cons
     if (best_i >= 0) cache_store(cache_path, key, *out, best);
     return DDHF_OK;
 }
+
+extern "C" int ddhf_autotune_scoring(const int32_t* row_ptr, const uint32_t* t_rel, const float* a,
+                                     const int32_t* active, int32_t n_active, int64_t n_events,
+                                     const ddhf_grid_t* grid, const ddhf_params_t* prm,
+                                     const ddhf_launch_t* launch, float* power, void* ws,
+                                     size_t ws_bytes, float* sf, float* snr_best,
+                                     int32_t* bin_best, int32_t* use_fused, float* ms_split,
+                                     float* ms_fused, void* stream) {
+    if (!use_fused || !grid || !prm || n_active < 0) return DDHF_EINVAL;
+    *use_fused = 0;
+    if (ms_split) *ms_split = -1.0f;
+    if (ms_fused) *ms_fused = -1.0f;
+    if (n_active == 0) return DDHF_OK;
+    hipStream_t s = as_stream(stream);
+    hipEvent_t e0, e1;
+    DDHF_TRY_HIP(hipEventCreate(&e0));
+    DDHF_TRY_HIP(hipEventCreate(&e1));
+    // times one form: a warm-up, then the best of five
+    auto time_form = [&](bool fused, float* best) -> int {
+        *best = 3.0e38f;
+        for (int rep = 0; rep < 6; ++rep) {
+            if (hipEventRecord(e0, s) != hipSuccess) return DDHF_EHIP;
+            int rc;
+            if (fused) {
+                rc = ndft_comb_run(row_ptr, t_rel, a, active, n_active, grid, prm, sf, snr_best,
+                                   bin_best, s);
+            } else {
+                rc = ndft_run(row_ptr, t_rel, a, active, n_active, nullptr, n_events, grid, power,
+                              launch, ws, ws_bytes, s);
+                if (!rc)
+                    rc = comb_run(power, n_active, nullptr, grid, prm, sf, snr_best, bin_best,
+                                  nullptr, s);
+            }
+            if (rc) return rc;
+            if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess)
+                return DDHF_EHIP;
+            float ms = 0.0f;
+            if (hipEventElapsedTime(&ms, e0, e1) != hipSuccess) return DDHF_EHIP;
+            if (rep > 0 && ms < *best) *best = ms;
+        }
+        return DDHF_OK;
+    };
+    float t_split = -1.0f, t_fused = -1.0f;
+    int rc = time_form(false, &t_split);
+    if (!rc) {
+        const int rf = time_form(true, &t_fused);
+        if (rf == DDHF_EINVAL) t_fused = -1.0f;  // the fused kernel does not cover this shape
+        else rc = rf;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (rc) return rc;
+    if (ms_split) *ms_split = t_split;
+    if (ms_fused) *ms_fused = t_fused;
+    // the fused kernel must win by 2 %, as a launch candidate must
+    *use_fused = (t_fused > 0.0f && t_fused < 0.98f * t_split) ? 1 : 0;
+    if (!*use_fused && t_fused > 0.0f) {
+        // the fused form ran last: leave the chosen form's scores behind
+        rc = ndft_run(row_ptr, t_rel, a, active, n_active, nullptr, n_events, grid, power, launch,
+                      ws, ws_bytes, s);
+        if (!rc) rc = comb_run(power, n_active, nullptr, grid, prm, sf, snr_best, bin_best,
+                               nullptr, s);
+    }
+    return rc;
+}

@@ -185,6 +185,21 @@ def ddhf_autotune(row_ptr, t_rel, a, active, n_active, n_events, grid: Grid, pow
     return out, ms.value
 
 
+def ddhf_autotune_scoring(row_ptr, t_rel, a, active, n_active, n_events, grid: Grid,
+                          prm: Params, launch: Optional[Launch], power, ws, sf, snr_best,
+                          bin_best, stream=None):
+    use = C.c_int32(0)
+    ms_s, ms_f = C.c_float(0), C.c_float(0)
+    rc = lib().ddhf_autotune_scoring(_p(row_ptr), _p(t_rel), _p(a), _p(active),
+                                     C.c_int32(n_active), C.c_int64(n_events), C.byref(grid),
+                                     C.byref(prm), C.byref(launch) if launch is not None else None,
+                                     _p(power), _p(ws), C.c_size_t(ws.numel()), _p(sf),
+                                     _p(snr_best), _p(bin_best), C.byref(use), C.byref(ms_s),
+                                     C.byref(ms_f), _stream(stream))
+    _check(rc, "ddhf_autotune_scoring")
+    return bool(use.value), ms_s.value, ms_f.value
+
+
 def ddhf_comb_score(power, n_active, grid: Grid, prm: Params, sf, snr_best, bin_best,
                     snr_all=None, stream=None):
     rc = lib().ddhf_comb_score(_p(power), C.c_int32(n_active), C.byref(grid), C.byref(prm),
@@ -353,6 +368,18 @@ class Window:
         self.ws_ndft = workspace(ddhf_ndft_workspace_size(max(self.n_active, 1), self.n,
                                                           self.grid, launch), self.dev)
         return launch, ms
+
+    def select_scoring(self, stream=None):
+        """Times the spectra + comb pair (with this window's launch) against the
+        fused kernel and keeps the faster; returns (fused, ms_split, ms_fused)."""
+        self.fused = False
+        self.alloc_spectra()
+        use, ms_s, ms_f = ddhf_autotune_scoring(self.row_ptr, self.t_rel, self.a, self.active,
+                                                self.n_active, self.n, self.grid, self.prm,
+                                                self.launch, self.power, self.ws_ndft, self.sf,
+                                                self.snr, self.bin, stream)
+        self.fused = bool(use)
+        return self.fused, ms_s, ms_f
 
     def spectra(self, stream=None):
         ddhf_ndft_power(self.row_ptr, self.t_rel, self.a, self.active, self.n_active, self.n,

@@ -225,3 +225,37 @@ def test_fused_unsupported_shapes_are_refused():
     g.alloc_spectra()
     with pytest.raises(D.DdhfError):
         g.spectra_and_score()
+
+
+def test_scoring_selector():
+    """ddhf_autotune_scoring times both forms, returns positive times, and the
+    window then scores with the chosen one; the scores it leaves behind equal
+    the two-call path's or the fused kernel's."""
+    win = synth.medium_window(2)
+    g = D.window_from_synth(win, device=DEV, order_by_cost=True,
+                            launch=D.make_launch(D.DDHF_KERNEL_MFMA16, 64))
+    g.index()
+    g.fetch_n_active()
+    fused, ms_s, ms_f = g.select_scoring()
+    banner(f"scoring selector: fused={fused} split {ms_s:.3f} ms fused {ms_f:.3f} ms")
+    assert ms_s > 0 and ms_f > 0
+    assert fused == (ms_f < 0.98 * ms_s)
+    na = g.n_active
+    sel = (g.sf[:na].clone(), g.snr[:na].clone(), g.bin[:na].clone())
+    g.fused = False
+    g.alloc_spectra()
+    g.spectra_and_score()
+    split = (g.sf[:na].clone(), g.snr[:na].clone(), g.bin[:na].clone())
+    f = fused_scores(win)
+    fz = (f.sf[:na], f.snr[:na], f.bin[:na])
+    ref = fz if fused else split
+    for a, b in zip(sel, ref):
+        assert torch.equal(a, b)
+    # a shape only the two-call path covers: the fused form is reported absent
+    win2 = counts_window([5, 9, 40], 20_000, Grid(f0=1000, df=1000, K=5000, mode=0),
+                         Params(n_min=1))
+    h = D.window_from_synth(win2, device=DEV, launch=D.make_launch(D.DDHF_KERNEL_MFMA16, 64))
+    h.index()
+    h.fetch_n_active()
+    fused2, ms_s2, ms_f2 = h.select_scoring()
+    assert not fused2 and ms_s2 > 0 and ms_f2 == -1.0
