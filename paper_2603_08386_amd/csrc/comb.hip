@@ -515,8 +515,10 @@ __device__ __forceinline__ void comb_fast_pixel(const CombArgs& ca, int32_t u, i
         for (int j = 0; j < kFastItems; ++j) {
             if (in_seg(full, j, nmine)) {
                 fsum += v[j];
+                // word pad8(d) = d + d / 8 of d = bits 20..29; bit 30 picks the half
                 const uint32_t b = __float_as_uint(v[j]);
-                atomicAdd(&sX[pad8((int)((b >> 20) & 0x3FFu))], 1u << ((b >> 26) & 16u));
+                const uint32_t w = __builtin_amdgcn_ubfe(b, 20, 10) + __builtin_amdgcn_ubfe(b, 23, 7);
+                atomicAdd(&sX[w], __builtin_amdgcn_ubfe(b, 30, 1) * 0xFFFFu + 1u);
             }
         }
     });
@@ -525,6 +527,9 @@ __device__ __forceinline__ void comb_fast_pixel(const CombArgs& ca, int32_t u, i
     const float floor_v = (float)(ca.eps * mean);
     locate_x2<1>(sX, 0, ca.b_lo, &l1lo, 0, ca.b_hi, &l1hi, scr);
     const uint32_t d1lo = (uint32_t)l1lo.d, d1hi = (uint32_t)l1hi.d;
+    // P >= 0, so bit 31 is clear and the digit is b >> 20: the bucket range
+    // [d1lo, d1hi] is the bit-pattern range [d1lo << 20, (d1hi + 1) << 20)
+    const uint32_t b1lo = d1lo << 20, b1span = ((d1hi - d1lo + 1u) << 20) - 1u;
 #pragma unroll
     for (int i = 0; i < kHistWords / kFT; ++i) sX[tid + i * kFT] = 0u;
     __syncthreads();
@@ -535,13 +540,13 @@ __device__ __forceinline__ void comb_fast_pixel(const CombArgs& ca, int32_t u, i
     seg_dispatch(nmine, [&](auto full) {
 #pragma unroll
         for (int j = 0; j < kFastItems; ++j)
-            lg[j] = in_seg(full, j, nmine) ? __log2f(v[j] > floor_v ? v[j] : floor_v) : 0.0f;
+            lg[j] = in_seg(full, j, nmine) ? __log2f(fmaxf(v[j], floor_v)) : 0.0f;
 #pragma unroll
         for (int j = 0; j < kFastItems; ++j) {
             const uint32_t b = __float_as_uint(v[j]);
-            const uint32_t d1 = (b >> 20) & 0x7FFu;
             // one range test: few bins fall in [d1lo, d1hi]
-            if (in_seg(full, j, nmine) && d1 - d1lo <= d1hi - d1lo) {
+            if (in_seg(full, j, nmine) && b - b1lo <= b1span) {
+                const uint32_t d1 = b >> 20;
                 const int d2 = pad8((int)((b >> 10) & 0x3FFu));
                 const uint32_t inc = (d1 == d1lo ? 1u : 0u) + (d1 == d1hi ? 1u << 16 : 0u);
                 if (inc) atomicAdd(&sX[d2], inc);
@@ -576,14 +581,17 @@ __device__ __forceinline__ void comb_fast_pixel(const CombArgs& ca, int32_t u, i
     {
         // candidates of the segment as a bit mask; one list append per wavefront
         uint32_t cmask = 0u;
+        // the 21-bit key is b >> 10 (bit 31 clear): key < key_lo iff b < key_lo << 10,
+        // key > key_hi iff b >= (key_hi + 1) << 10
+        const uint32_t blo = key_lo << 10, bhi = (key_hi + 1u) << 10;
         seg_dispatch(nmine, [&](auto full) {
 #pragma unroll
             for (int j = 0; j < kFastItems; ++j) {
                 if (in_seg(full, j, nmine)) {
-                    const uint32_t kk = (__float_as_uint(v[j]) >> 10) & 0x1FFFFFu;
-                    const uint8_t code =
-                        kk < key_lo ? kCodeBelow : (kk > key_hi ? kCodeAbove : kCodeCand);
-                    cmask |= (code == kCodeCand ? 1u : 0u) << j;
+                    const uint32_t b = __float_as_uint(v[j]);
+                    const bool cand = b - blo < bhi - blo;
+                    const uint8_t code = cand ? kCodeCand : (b < blo ? kCodeBelow : kCodeAbove);
+                    cmask |= (cand ? 1u : 0u) << j;
                     sCode[s0 + j] = code;
                 }
             }
@@ -621,11 +629,15 @@ __device__ __forceinline__ void comb_fast_pixel(const CombArgs& ca, int32_t u, i
         const float vi = mine ? sP[padk(ki)] : 0.0f;
         const int q = (nL + kFT / kWave - 1) / (kFT / kWave);
         const int b1 = (w + 1) * q < nL ? (w + 1) * q : nL;
+        // (value, bin) as one 44-bit key: P >= 0, so the bit pattern orders values
+        const uint32_t khi = __float_as_uint(vi) >> 20;
+        const uint32_t klo = (__float_as_uint(vi) << 12) | (uint32_t)ki;
+        const uint64_t key = ((uint64_t)khi << 32) | klo;
         uint32_t r = 0;
         for (int b = w * q; b < b1; ++b) {
-            const float vj = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(vi), b));
-            const int kj = __builtin_amdgcn_readlane(ki, b);
-            r += (vj < vi || (vj == vi && kj < ki)) ? 1u : 0u;
+            const uint64_t kb = ((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)khi, b) << 32) |
+                                (uint32_t)__builtin_amdgcn_readlane((int)klo, b);
+            r += kb < key ? 1u : 0u;
         }
         if (mine && r) atomicAdd(&s_rank[lane], r);
         __syncthreads();
@@ -728,34 +740,42 @@ __device__ __forceinline__ void comb_fast_pixel(const CombArgs& ca, int32_t u, i
             bool spill = false;
             int inr[kInbCap];
             int ph = -1;
+            int q_fast = 0;   // median's band index, when the fast form finds it
+            bool fast = false;
             if (MT > 0 && DKT >= 0 && mv == MT && i > 2 * dk) {
                 // every window inside the spectrum and disjoint (centres at
-                // least i > 2 dk apart): all reads issued together
+                // least i > 2 dk apart): all reads issued together, and the
+                // fixed point counts the window's band codes directly (band
+                // indices are below kCodeCand, so c <= q < kCodeCand selects them)
                 constexpr int D = DKT >= 0 ? DKT : 0;
                 constexpr int MM = MT > 0 ? MT : 1;
+                constexpr int NW = MM * (2 * D + 1);
                 float wmv[MM];
-                uint8_t cw[MM][2 * D + 1];
+                uint32_t cw[NW];
 #pragma unroll
                 for (int m = 1; m <= MM; ++m) {
                     const int cm = centre_of(i, m);
                     wmv[m - 1] = sP[padk(cm)];
 #pragma unroll
-                    for (int q = 0; q <= 2 * D; ++q) cw[m - 1][q] = sCode[padk(cm - D + q)];
+                    for (int q = 0; q <= 2 * D; ++q)
+                        cw[(m - 1) * (2 * D + 1) + q] = sCode[padk(cm - D + q)];
                 }
 #pragma unroll
-                for (int m = 0; m < MM; ++m) {
-                    smax += wmv[m];
+                for (int m = 0; m < MM; ++m) smax += wmv[m];
 #pragma unroll
-                    for (int q = 0; q <= 2 * D; ++q) {
-                        const uint8_t c = cw[m][q];
-                        below += c == kCodeBelow ? 1 : 0;
-                        if (c < kCodeCand) {
-                            if (nin < kInbCap) inr[nin++] = (int)c;
-                            else spill = true;
-                        }
-                    }
+                for (int k = 0; k < NW; ++k) below += cw[k] == kCodeBelow ? 1 : 0;
+                const int t = (K - NW - 1) / 2 + below - ca.b_lo;
+                int q = t;
+                for (int iter = 0; iter <= NW; ++iter) {
+                    int extra = 0;
+#pragma unroll
+                    for (int k = 0; k < NW; ++k) extra += (int)cw[k] <= q ? 1 : 0;
+                    if (t + extra == q) break;
+                    q = t + extra;
                 }
-                hsize = MM * (2 * D + 1);
+                hsize = NW;
+                q_fast = q;
+                fast = true;
                 ph = K;  // the general loop below is skipped
             }
             for (int m = 1; m <= mv && ph < K; ++m) {
@@ -794,8 +814,8 @@ __device__ __forceinline__ void comb_fast_pixel(const CombArgs& ca, int32_t u, i
             }
             // band index of the median: smallest q with q = t + #(window band indices <= q)
             const int t = (K - hsize - 1) / 2 + below - ca.b_lo;
-            int q = t;
-            for (int iter = 0; iter <= hsize; ++iter) {
+            int q = fast ? q_fast : t;
+            for (int iter = 0; iter <= hsize && !fast; ++iter) {
                 int extra = 0;
                 if (!spill) {
                     for (int j = 0; j < nin; ++j) extra += inr[j] <= q ? 1 : 0;
@@ -837,7 +857,8 @@ __device__ __forceinline__ void comb_fast_pixel(const CombArgs& ca, int32_t u, i
     bool every = snr_all != nullptr || !(den_lo > 0.0f);
     int n_eval = 0;
     if (!every) {
-        const float r_hi = 1.0f / den_hi, r_lo = 1.0f / den_lo;
+        // reciprocals to within one ulp: the bounds' margin covers them
+        const float r_hi = __builtin_amdgcn_rcpf(den_hi), r_lo = __builtin_amdgcn_rcpf(den_lo);
         // N of candidate i (the value the exact evaluation uses), -1 if inadmissible
         // (centres grow with m, so the valid harmonics are a prefix; the
         // reciprocal is approximate, which the bounds' margin covers)
