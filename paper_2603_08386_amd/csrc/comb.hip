@@ -378,19 +378,10 @@ struct Loc {
     uint32_t before;
 };
 
-// Per-segment loops run with compile-time bounds in wavefronts whose threads'
-// 16 bins all lie inside [0, K) (every wave except the one holding bin K - 1),
-// and with a bounds test per bin otherwise.  The choice is per wavefront, so
-// that the one holding the end of the spectrum runs one path, not both.
-template <class F>
-__device__ __forceinline__ void seg_dispatch(int nmine, F&& f) {
-    if (__builtin_amdgcn_ballot_w64(nmine != kFastItems) == 0ull) f(std::true_type{});
-    else f(std::false_type{});
-}
-// bin j of the segment is inside [0, K): always when the segment is full
-template <class Full>
-__device__ __forceinline__ bool in_seg(Full, int j, int nmine) {
-    return Full::value || j < nmine;
+// The fast comb holds K rounded up to a wave's 64 x 16 bins; the bins from K on
+// are zeros.
+__host__ __device__ constexpr int fast_bins(int K) {
+    return (K + kWave * kFastItems - 1) / (kWave * kFastItems) * (kWave * kFastItems);
 }
 
 // Histograms hold 16-bit counters, two per word (a count never exceeds
@@ -475,9 +466,10 @@ __device__ __forceinline__ void comb_fast_pixel(const CombArgs& ca, int32_t u, i
     extern __shared__ __align__(16) char smem[];
     float* sP = (float*)smem;                       // [kpad]: spectrum, then window maxima
     uint32_t* sX = (uint32_t*)(sP + ca.kpad);       // histograms, then codes ...
-    uint8_t* sCode = (uint8_t*)sX;                  // [code_bytes(K)] one code per bin
-    uint16_t* sList = (uint16_t*)((char*)sX + code_bytes(ca.K));  // [kListCap] candidates
-    float* sBand = (float*)((char*)sX + code_bytes(ca.K) + 2 * kListCap);  // band values
+    const int kend = fast_bins(ca.K);                // bins held: K rounded up to a wave's 1024
+    uint8_t* sCode = (uint8_t*)sX;                  // [code_bytes(kend)] one code per bin
+    uint16_t* sList = (uint16_t*)((char*)sX + code_bytes(kend));  // [kListCap] candidates
+    float* sBand = (float*)((char*)sX + code_bytes(kend) + 2 * kListCap);  // band values
     __shared__ double red[kFT / kWave];
     __shared__ uint32_t scr[2 * kFT / kWave];
     __shared__ Loc l1lo, l1hi, l2lo, l2hi;
@@ -506,22 +498,32 @@ __device__ __forceinline__ void comb_fast_pixel(const CombArgs& ca, int32_t u, i
     float v[kFastItems];
     int nmine = K - k0;  // bins of this segment inside [0, K)
     nmine = nmine < 0 ? 0 : (nmine > kFastItems ? kFastItems : nmine);
+    // Every wave that holds a bin below K runs the per-bin passes on all 16 x
+    // 64 of its bins; those from K to kend are zeros (pads) written by fill.
+    // A pad adds 0 to the sum, counts into histogram bucket 0, which the
+    // atomics below take back (integer atomics commute, so no ordering is
+    // needed), gives a log term that is zeroed, and never becomes a candidate.
+    const bool live = (tid / kWave) * (kWave * kFastItems) < K;  // wave-uniform
+    const bool has_pad = live && (tid / kWave + 1) * (kWave * kFastItems) > K;
+    const uint32_t npad = (uint32_t)(kend - K);
     // ---- sum and first digit (bits 20..30) ----------------------------------
     float fsum = 0.0f;  // 16 terms per thread; the block sum is in FP64
-    seg_dispatch(nmine, [&](auto full) {
+    if (live) {
 #pragma unroll
-        for (int j = 0; j < kFastItems; ++j) v[j] = in_seg(full, j, nmine) ? sP[s0 + j] : 0.0f;
+        for (int j = 0; j < kFastItems; ++j) v[j] = sP[s0 + j];
 #pragma unroll
         for (int j = 0; j < kFastItems; ++j) {
-            if (in_seg(full, j, nmine)) {
-                fsum += v[j];
-                // word pad8(d) = d + d / 8 of d = bits 20..29; bit 30 picks the half
-                const uint32_t b = __float_as_uint(v[j]);
-                const uint32_t w = __builtin_amdgcn_ubfe(b, 20, 10) + __builtin_amdgcn_ubfe(b, 23, 7);
-                atomicAdd(&sX[w], __builtin_amdgcn_ubfe(b, 30, 1) * 0xFFFFu + 1u);
-            }
+            fsum += v[j];
+            // word pad8(d) = d + d / 8 of d = bits 20..29; bit 30 picks the half
+            const uint32_t b = __float_as_uint(v[j]);
+            const uint32_t w = __builtin_amdgcn_ubfe(b, 20, 10) + __builtin_amdgcn_ubfe(b, 23, 7);
+            atomicAdd(&sX[w], __builtin_amdgcn_ubfe(b, 30, 1) * 0xFFFFu + 1u);
         }
-    });
+        if (tid == 0 && npad) atomicSub(&sX[0], npad);  // the pads' bucket-0 counts
+    } else {
+#pragma unroll
+        for (int j = 0; j < kFastItems; ++j) v[j] = 0.0f;
+    }
     const double sum = block_sum_d<kFT>((double)fsum, red);
     const double mean = sum / (double)K;
     const float floor_v = (float)(ca.eps * mean);
@@ -537,22 +539,36 @@ __device__ __forceinline__ void comb_fast_pixel(const CombArgs& ca, int32_t u, i
     // log2 terms summed pairwise in FP32 within the segment (16 terms, error
     // a few ulps of the segment sum), then across segments in FP64
     float lg[kFastItems];
-    seg_dispatch(nmine, [&](auto full) {
+    if (live) {
+        // max(P, floor) on the bit patterns (both >= 0: integer order is value order)
+        const uint32_t fb = __float_as_uint(floor_v);
 #pragma unroll
         for (int j = 0; j < kFastItems; ++j)
-            lg[j] = in_seg(full, j, nmine) ? __log2f(fmaxf(v[j], floor_v)) : 0.0f;
+            lg[j] = __log2f(__uint_as_float(max(__float_as_uint(v[j]), fb)));
+        if (has_pad) {
+#pragma unroll
+            for (int j = 0; j < kFastItems; ++j) lg[j] = j < nmine ? lg[j] : 0.0f;
+        }
 #pragma unroll
         for (int j = 0; j < kFastItems; ++j) {
             const uint32_t b = __float_as_uint(v[j]);
             // one range test: few bins fall in [d1lo, d1hi]
-            if (in_seg(full, j, nmine) && b - b1lo <= b1span) {
+            if (b - b1lo <= b1span) {
                 const uint32_t d1 = b >> 20;
                 const int d2 = pad8((int)((b >> 10) & 0x3FFu));
                 const uint32_t inc = (d1 == d1lo ? 1u : 0u) + (d1 == d1hi ? 1u << 16 : 0u);
                 if (inc) atomicAdd(&sX[d2], inc);
             }
         }
-    });
+        // pads (value 0: digit 0, second digit 0) counted where bucket 0 is an end bucket
+        if (tid == 0 && npad) {
+            const uint32_t take = (d1lo == 0u ? npad : 0u) + (d1hi == 0u ? npad << 16 : 0u);
+            if (take) atomicSub(&sX[0], take);
+        }
+    } else {
+#pragma unroll
+        for (int j = 0; j < kFastItems; ++j) lg[j] = 0.0f;
+    }
 #pragma unroll
     for (int h = kFastItems / 2; h >= 1; h >>= 1) {
 #pragma unroll
@@ -584,18 +600,17 @@ __device__ __forceinline__ void comb_fast_pixel(const CombArgs& ca, int32_t u, i
         // the 21-bit key is b >> 10 (bit 31 clear): key < key_lo iff b < key_lo << 10,
         // key > key_hi iff b >= (key_hi + 1) << 10
         const uint32_t blo = key_lo << 10, bhi = (key_hi + 1u) << 10;
-        seg_dispatch(nmine, [&](auto full) {
+        if (live) {
 #pragma unroll
             for (int j = 0; j < kFastItems; ++j) {
-                if (in_seg(full, j, nmine)) {
-                    const uint32_t b = __float_as_uint(v[j]);
-                    const bool cand = b - blo < bhi - blo;
-                    const uint8_t code = cand ? kCodeCand : (b < blo ? kCodeBelow : kCodeAbove);
-                    cmask |= (cand ? 1u : 0u) << j;
-                    sCode[s0 + j] = code;
-                }
+                const uint32_t b = __float_as_uint(v[j]);
+                const bool cand = b - blo < bhi - blo;
+                const uint8_t code = cand ? kCodeCand : (b < blo ? kCodeBelow : kCodeAbove);
+                cmask |= (cand ? 1u : 0u) << j;
+                sCode[s0 + j] = code;
             }
-        });
+            if (has_pad) cmask &= (1u << nmine) - 1u;  // pads are never candidates
+        }
         const uint32_t cnt = (uint32_t)__popc(cmask);
         const uint32_t incl = wave_incl_scan(cnt);
         uint32_t base = 0u;
@@ -707,11 +722,10 @@ __device__ __forceinline__ void comb_fast_pixel(const CombArgs& ca, int32_t u, i
             }
         }
         __syncthreads();  // every read of the spectrum is done; codes and band are complete
-        seg_dispatch(nmine, [&](auto full) {
+        if (live) {
 #pragma unroll
-            for (int j = 0; j < kFastItems; ++j)
-                if (in_seg(full, j, nmine)) sP[s0 + j] = wm[j];
-        });
+            for (int j = 0; j < kFastItems; ++j) sP[s0 + j] = wm[j];
+        }
     }
     __syncthreads();
     // ---- candidates (Eq. 8-11) ----------------------------------------------
@@ -980,9 +994,10 @@ __global__ __launch_bounds__(kFT) void k_comb_fast(const float* __restrict__ pow
             g[i] = k < ca.K ? row[k] : 0.0f;
         }
         const int ps = padk(tid);
+        const int kend = fast_bins(ca.K);
 #pragma unroll
         for (int i = 0; i < kFastItems; ++i)
-            if (tid + i * kFT < ca.K) sP[ps + i * (kFT + (kFT >> kSegShift))] = g[i];
+            if (tid + i * kFT < kend) sP[ps + i * (kFT + (kFT >> kSegShift))] = g[i];  // pads: 0
     });
 }
 
@@ -1117,6 +1132,7 @@ __global__ __launch_bounds__(kFT) void k_ndft_comb(const int32_t* __restrict__ r
             const int j = 1024 * w + 32 * row + (int)r32;
             if (j < ca.K) sP[padk(j)] = cre[r] * cre[r] + cim[r] * cim[r];
         }
+        for (int j = ca.K + tid; j < fast_bins(ca.K); j += kFT) sP[padk(j)] = 0.0f;  // pads
     });
 }
 
@@ -1202,8 +1218,10 @@ static CombSetup comb_setup(const ddhf_grid_t* grid, const ddhf_params_t* prm) {
     cs.fast = ca.K <= 4096 && bw <= 253;
     cs.lds = 0;
     if (cs.fast) {
-        ca.kpad = ((ca.K - 1) + ((ca.K - 1) >> kSegShift) + 1 + 3) / 4 * 4;  // padded bin array
-        cs.lds = (size_t)ca.kpad * 4 + (size_t)x_bytes(ca.K, bw);
+        // padded bin array for the bins up to the end of the last wave's segments
+        const int kend = fast_bins(ca.K);
+        ca.kpad = ((kend - 1) + ((kend - 1) >> kSegShift) + 1 + 3) / 4 * 4;
+        cs.lds = (size_t)ca.kpad * 4 + (size_t)x_bytes(kend, bw);
     }
     return cs;
 }
