@@ -549,16 +549,21 @@ __device__ __forceinline__ void comb_fast_pixel(const CombArgs& ca, int32_t u, i
 #pragma unroll
             for (int j = 0; j < kFastItems; ++j) lg[j] = j < nmine ? lg[j] : 0.0f;
         }
+        // few bins fall in [d1lo, d1hi] (a few per cent): mark them branch-free,
+        // then visit the marked ones (re-read from LDS) one at a time
+        uint32_t l2m = 0u;
 #pragma unroll
-        for (int j = 0; j < kFastItems; ++j) {
-            const uint32_t b = __float_as_uint(v[j]);
-            // one range test: few bins fall in [d1lo, d1hi]
-            if (b - b1lo <= b1span) {
-                const uint32_t d1 = b >> 20;
-                const int d2 = pad8((int)((b >> 10) & 0x3FFu));
-                const uint32_t inc = (d1 == d1lo ? 1u : 0u) + (d1 == d1hi ? 1u << 16 : 0u);
-                if (inc) atomicAdd(&sX[d2], inc);
-            }
+        for (int j = 0; j < kFastItems; ++j)
+            l2m |= (__float_as_uint(v[j]) - b1lo <= b1span ? 1u : 0u) << j;
+        const uint32_t b1hi = d1hi << 20;
+        while (l2m) {
+            const int j = __builtin_ctz(l2m);
+            l2m &= l2m - 1u;
+            const uint32_t b = __float_as_uint(sP[s0 + j]);
+            // word pad8(d2) of the second digit d2 = bits 10..19
+            const uint32_t w = __builtin_amdgcn_ubfe(b, 10, 10) + __builtin_amdgcn_ubfe(b, 13, 7);
+            const uint32_t inc = (b - b1lo < (1u << 20) ? 1u : 0u) + (b >= b1hi ? 1u << 16 : 0u);
+            atomicAdd(&sX[w], inc);
         }
         // pads (value 0: digit 0, second digit 0) counted where bucket 0 is an end bucket
         if (tid == 0 && npad) {
@@ -948,8 +953,54 @@ __device__ __forceinline__ void comb_fast_pixel(const CombArgs& ca, int32_t u, i
         if (n_eval > kListCap) every = true;  // uniform
     }
     if (every) n_eval = i_max - dk + 1;
-    // one inlined copy of the exact evaluation serves both forms
-    for (int e = tid; e < n_eval; e += kFT) eval_exact(every ? dk + e : (int)sList[e]);
+    if (!every && MT > 0 && DKT >= 0) {
+        // The survivors, one per wavefront at a time: lane l < NW reads the code
+        // of window bin l, and the counts of the median's fixed point come from
+        // ballots (the same arithmetic as eval_exact's first form, spread over
+        // the lanes instead of serial in one).
+        constexpr int D = DKT >= 0 ? DKT : 0;
+        constexpr int MM = MT > 0 ? MT : 1;
+        constexpr int W2 = 2 * D + 1;
+        constexpr int NW = MM * W2;
+        static_assert(NW <= kWave, "one window bin per lane");
+        const int lane = __lane_id();
+        for (int e = tid / kWave; e < n_eval; e += kFT / kWave) {
+            const int i = __builtin_amdgcn_readfirstlane((int)sList[e]);
+            const int mv = n_valid(i);
+            if (mv == MM && i > 2 * dk) {
+                uint32_t c = kCodeAbove;  // lanes past the windows count nowhere
+                if (lane < NW) c = sCode[padk(centre_of(i, lane / W2 + 1) - D + lane % W2)];
+                float smax = sP[padk(centre_of(i, 1))];
+#pragma unroll
+                for (int m = 2; m <= MM; ++m) smax += sP[padk(centre_of(i, m))];
+                const int below = (int)__popcll(__builtin_amdgcn_ballot_w64(c == kCodeBelow));
+                const int t = (K - NW - 1) / 2 + below - ca.b_lo;
+                int q = t;
+                for (int iter = 0; iter <= NW; ++iter) {
+                    const int extra = (int)__popcll(__builtin_amdgcn_ballot_w64((int)c <= q));
+                    if (t + extra == q) break;
+                    q = t + extra;
+                }
+                float med = 0.0f;
+                if (K - NW > 0) {
+                    q = q < 0 ? 0 : (q > bw ? bw : q);
+                    med = sBand[q];
+                }
+                const float N = smax / (float)mv;
+                const float den = med > fden_floor ? med : fden_floor;
+                const float snr = den > 0.0f ? __fdividef(N, den) : 0.0f;
+                if (lane == 0 && (best_i < 0 || snr > best || (snr == best && i < best_i))) {
+                    best = snr;
+                    best_i = i;
+                }
+            } else if (lane == 0) {
+                eval_exact(i);  // overlapping windows or harmonics outside the spectrum
+            }
+        }
+    } else {
+        // one inlined copy of the exact evaluation serves both forms
+        for (int e = tid; e < n_eval; e += kFT) eval_exact(every ? dk + e : (int)sList[e]);
+    }
     if (snr_all) {
         for (int i = tid; i < K; i += kFT)
             if (i < dk || i > i_max) snr_all[(int64_t)u * K + i] = 0.0f;
