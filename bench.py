@@ -121,7 +121,8 @@ def _pmc_mean_kib(path, counter, name_part):
 
 
 # sources whose digest keys a traffic record
-TRAFFIC_SOURCES = {"ndft": ["ndft.hip", "ddhf_internal.h"], "comb": ["comb.hip", "ddhf_internal.h"]}
+TRAFFIC_SOURCES = {"ndft": ["ndft.hip", "phase.h", "ddhf_internal.h"],
+                   "comb": ["comb.hip", "phase.h", "ddhf_internal.h"]}
 
 
 KERNEL_NAMES = {0: "valu", 1: "mfma", 2: "mfma16"}
