@@ -788,7 +788,7 @@ def test_autotune_picks_a_valid_launch_and_caches(tmp_path):
     g.alloc_spectra()
     cache = str(tmp_path / "tune.jsonl")
     launch, ms = g.autotune(cache)
-    assert ms > 0 and launch.kernel in (0, 1)
+    assert ms > 0 and launch.kernel in (D.DDHF_KERNEL_VALU, D.DDHF_KERNEL_MFMA, D.DDHF_KERNEL_MFMA16)
     # a second call hits the cache and returns the same launch
     launch2, ms2 = g.autotune(cache)
     assert ms2 == -1.0
