@@ -210,15 +210,34 @@ def test_ndft_deterministic(kernel, bpl):
     assert np.array_equal(P1, P2)
 
 
-def test_ndft_empty_and_degenerate():
+@pytest.mark.parametrize("kernel,bpl,rtol", [(0, 32, 1e-6), (1, 64, 1e-6), (2, 64, 1e-5), (2, 16, 1e-5)])
+def test_ndft_empty_and_degenerate(kernel, bpl, rtol):
+    """No events; one event (|a|^2 at every bin: the split-FP16 products carry
+    about 2^-20 relative error per term); a pixel whose events all have zero
+    weight (a zero spectrum, and no amplitude scale to take)."""
     grid = Grid(f0=1000, df=1000, K=300)
+    launch = D.make_launch(kernel, bpl)
     win = synth.random_window(30, 8, 8, 1000, 0, grid, params=Params(n_min=1))
-    g, P = gpu_power(win)
+    g, P = gpu_power(win, launch)
     assert g.n_active == 0
     # a single event in a single pixel: |a|^2 everywhere
     win = synth.random_window(31, 1, 1, 1000, 1, grid, params=Params(n_min=1))
-    g, P = gpu_power(win)
-    assert np.allclose(P, 1.0, rtol=1e-6)
+    g, P = gpu_power(win, launch)
+    assert np.allclose(P, 1.0, rtol=rtol)
+    # two pixels, the second with zero-weight events only
+    base = synth.random_window(32, 2, 1, 20_000, 40, grid, params=Params(n_min=1))
+    w = np.where(base.x == 1, 0.0, 1.0).astype(np.float32)
+    g = D.Window(base.x, base.y, base.p, base.t, base.W, base.H, base.t0, base.T_w, grid,
+                 base.params, w=w, device=DEV, launch=launch)
+    g.index()
+    g.fetch_n_active()
+    g.alloc_spectra()
+    g.spectra()
+    torch.cuda.synchronize()
+    P = to_np(g.power, g.n_active * grid.K).reshape(g.n_active, grid.K)
+    act = to_np(g.active, g.n_active)
+    assert act.tolist() == [0, 1]
+    assert np.all(P[1] == 0.0) and np.all(P[0] > 0.0)
 
 
 @pytest.mark.parametrize("kernel,bpl,split", [(1, 64, 0), (2, 64, 0), (2, 32, 40), (2, 16, 0)])
