@@ -259,9 +259,11 @@ int ddhf_comb_score(const float* power, int32_t n_active, const ddhf_grid_t* gri
 /* ---- 4b. fused spectrum + flatness + comb (Eq. 6-11) --------------------- */
 
 /* The per-pixel order of Sec. 3.5 in one kernel: for each active pixel u the
- * power spectrum of Eq. 6 (as ddhf_ndft_power defines it, FP32 matrix-core
- * products) is formed in on-chip memory and scored as ddhf_comb_score does;
- * the spectrum is never written to device memory.  Inputs as for
+ * power spectrum of Eq. 6 (as ddhf_ndft_power defines it) is formed in
+ * on-chip memory and scored as ddhf_comb_score does; the spectrum is never
+ * written to device memory.  launch (nullable) chooses the matrix products:
+ * kernel DDHF_KERNEL_MFMA16 (split FP16, the default) or DDHF_KERNEL_MFMA
+ * (FP32); its other fields are ignored, another kernel is DDHF_EINVAL.  Inputs as for
  * ddhf_ndft_power (row_ptr, t_rel, a from call 1; active, n_active from
  * call 2), outputs as for ddhf_comb_score (sf, snr_best, bin_best of
  * n_active entries; no per-candidate scores).  Needs K <= 4096 and a median
@@ -272,8 +274,8 @@ int ddhf_comb_score(const float* power, int32_t n_active, const ddhf_grid_t* gri
  * within the spectra's error bound (the spectrum's rounding differs). */
 int ddhf_ndft_comb(const int32_t* row_ptr, const uint32_t* t_rel, const float* a,
                    const int32_t* active, int32_t n_active, const ddhf_grid_t* grid,
-                   const ddhf_params_t* prm, float* sf, float* snr_best, int32_t* bin_best,
-                   void* stream);
+                   const ddhf_params_t* prm, const ddhf_launch_t* launch, float* sf,
+                   float* snr_best, int32_t* bin_best, void* stream);
 
 /* ---- 5. mask, components, boxes, merge (Sec. 3.5, Eq. 12) ---------------- */
 

@@ -188,6 +188,10 @@ extern "C" int ddhf_autotune_scoring(const int32_t* row_ptr, const uint32_t* t_r
     hipEvent_t e0, e1;
     DDHF_TRY_HIP(hipEventCreate(&e0));
     DDHF_TRY_HIP(hipEventCreate(&e1));
+    // the fused form takes the launch's matrix kernel, split-FP16 otherwise
+    ddhf_launch_t fl{};
+    if (launch) fl = *launch;
+    if (fl.kernel != DDHF_KERNEL_MFMA && fl.kernel != DDHF_KERNEL_MFMA16) fl.kernel = DDHF_KERNEL_MFMA16;
     // times one form: a warm-up, then the best of five
     auto time_form = [&](bool fused, float* best) -> int {
         *best = 3.0e38f;
@@ -195,8 +199,8 @@ extern "C" int ddhf_autotune_scoring(const int32_t* row_ptr, const uint32_t* t_r
             if (hipEventRecord(e0, s) != hipSuccess) return DDHF_EHIP;
             int rc;
             if (fused) {
-                rc = ndft_comb_run(row_ptr, t_rel, a, active, n_active, grid, prm, sf, snr_best,
-                                   bin_best, s);
+                rc = ndft_comb_run(row_ptr, t_rel, a, active, n_active, grid, prm, &fl, sf,
+                                   snr_best, bin_best, s);
             } else {
                 rc = ndft_run(row_ptr, t_rel, a, active, n_active, nullptr, n_events, grid, power,
                               launch, ws, ws_bytes, s);

@@ -1113,8 +1113,19 @@ __device__ __forceinline__ PairOps pair_operands(const EvFused& s, uint32_t mU, 
 
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 
-template <int MT, int DKT>
-__global__ __launch_bounds__(kFT) void k_ndft_comb(const int32_t* __restrict__ row_ptr,
+// The split-FP16 form (F16): the same products on the FP16 matrix cores, eight
+// events per v_mfma_f32_32x32x16_f16 (lane l holds k = 8 (l / 32) .. + 7:
+// events 4 (l / 32) .. + 3 of the group, for row / column l mod 32), each
+// operand split into two FP16 parts with three products accumulated in FP32,
+// and the pixel's amplitudes scaled by 2^-e, e = ceil(log2 max |a|), so that
+// no operand leaves the FP16 range (the power is scaled back exactly).
+// Register budget per wavefront: seven workgroups per CU (the comb's LDS
+// allows seven at K = 3991) need at most 72 VGPRs, which the M = 4, dk = 3 form
+// meets without spilling; the other forms get six and four.
+constexpr int fused_min_waves(int mt, int dkt) { return (mt == 4 && dkt == 3) ? 7 : (mt > 0 ? 6 : 4); }
+
+template <int MT, int DKT, bool F16>
+__global__ __launch_bounds__(kFT, fused_min_waves(MT, DKT)) void k_ndft_comb(const int32_t* __restrict__ row_ptr,
                                                    const uint32_t* __restrict__ t_rel,
                                                    const float* __restrict__ av,
                                                    const int32_t* __restrict__ active,
@@ -1127,6 +1138,98 @@ __global__ __launch_bounds__(kFT) void k_ndft_comb(const int32_t* __restrict__ r
     if (u >= n_active) return;
     const int32_t px = active[u];
     const int32_t beg = row_ptr[px], end = row_ptr[px + 1];
+    __shared__ float s_amax[kFT / kWave];
+    if constexpr (F16) {
+        comb_fast_pixel<MT, DKT>(ca, u, i_max, i_all, sf_out, snr_out, bin_out, nullptr,
+                                 [&](float* sP) {
+            EvFused* st = (EvFused*)(sP + ca.kpad);
+            const int tid = threadIdx.x;
+            const int lane = tid & (kWave - 1);
+            const int w = tid / kWave;
+            const int kb = lane >> 5;                             // events 4 kb .. 4 kb + 3
+            const uint32_t r32 = (uint32_t)(lane & 31);
+            const uint32_t mU = 1024u * (uint32_t)w + 32u * r32;  // U row r32 of tile w
+            const bool live = 1024 * w < ca.K;                     // wave-uniform
+            // the pixel's amplitude scale
+            float amax = 0.0f;
+            for (int32_t e = beg + tid; e < end; e += kFT) amax = fmaxf(amax, fabsf(av[e]));
+            amax = wave_max(amax);
+            if (lane == 0) s_amax[w] = amax;
+            __syncthreads();
+#pragma unroll
+            for (int q = 0; q < kFT / kWave; ++q) amax = fmaxf(amax, s_amax[q]);
+            int ex = 0;
+            if (amax > 0.0f) {
+                const float m = frexpf(amax, &ex);  // amax = m 2^ex, m in [1/2, 1)
+                if (m == 0.5f) --ex;
+            }
+            const float sc = ldexpf(1.0f, -ex);
+            f32x16 cre, cim;
+#pragma unroll
+            for (int r = 0; r < 16; ++r) { cre[r] = 0.0f; cim[r] = 0.0f; }
+            for (int32_t c0 = beg; c0 < end; c0 += kFuseChunk) {
+                {
+                    // stage: entries past the pixel's end carry zero weight
+                    const int32_t e = c0 + tid;
+                    EvFused s{0u, 0u, 0u, 0.0f};
+                    if (e < end) {
+                        const uint64_t t = t_rel[e];
+                        const uint32_t A = mod_q((uint64_t)g.f0 * t, g);
+                        const uint32_t D = mod_q((uint64_t)g.df * t, g);
+                        const Frac f = make_frac(A, D, g);
+                        s.phiA = f.phiA;
+                        s.q1 = (uint32_t)(f.F >> 16);
+                        s.q2 = (uint32_t)(f.F & 0xFFFFu);
+                        s.a = av[e] * sc;
+                    }
+                    st[tid] = s;
+                }
+                __syncthreads();
+                const int ne = (end - c0) < kFuseChunk ? (end - c0) : kFuseChunk;
+                if (live) {
+                    for (int k0 = 0; k0 < ne; k0 += 8) {
+                        u32x4 brh, brl, bih, bil, ah, al;
+#pragma unroll
+                        for (int q = 0; q < 4; ++q) {
+                            const EvFused sv = st[k0 + 4 * kb + q];
+                            float vs, vc, sn, cs;
+                            sincos_rev(frac_phase12(0u, sv.q1, sv.q2, r32), vs, vc);
+                            sincos_rev(frac_phase12(sv.phiA, sv.q1, sv.q2, mU), sn, cs);
+                            // B (real part): (Re V, -Im V); B (imaginary part): (Im V, Re V)
+                            const uint32_t h =
+                                __builtin_bit_cast(uint32_t, __builtin_amdgcn_cvt_pkrtz(vc, -vs));
+                            const float dr = sub_f16lo(vc, h), di = sub_f16hi(-vs, h);
+                            brh[q] = h;
+                            brl[q] = __builtin_bit_cast(uint32_t, __builtin_amdgcn_cvt_pkrtz(dr, di));
+                            bih[q] = __builtin_bit_cast(uint32_t, __builtin_amdgcn_cvt_pkrtz(vs, vc));
+                            bil[q] = __builtin_bit_cast(uint32_t, __builtin_amdgcn_cvt_pkrtz(-di, dr));
+                            uint32_t hq, lq;
+                            split_pk(cs * sv.a, sn * sv.a, hq, lq);
+                            ah[q] = hq;
+                            al[q] = lq;
+                        }
+                        const f16x8 Ah = as_f16x8(ah), Al = as_f16x8(al);
+                        cre = __builtin_amdgcn_mfma_f32_32x32x16_f16(Ah, as_f16x8(brh), cre, 0, 0, 0);
+                        cim = __builtin_amdgcn_mfma_f32_32x32x16_f16(Ah, as_f16x8(bih), cim, 0, 0, 0);
+                        cre = __builtin_amdgcn_mfma_f32_32x32x16_f16(Al, as_f16x8(brh), cre, 0, 0, 0);
+                        cim = __builtin_amdgcn_mfma_f32_32x32x16_f16(Al, as_f16x8(bih), cim, 0, 0, 0);
+                        cre = __builtin_amdgcn_mfma_f32_32x32x16_f16(Ah, as_f16x8(brl), cre, 0, 0, 0);
+                        cim = __builtin_amdgcn_mfma_f32_32x32x16_f16(Ah, as_f16x8(bil), cim, 0, 0, 0);
+                    }
+                }
+                __syncthreads();
+            }
+            const int half = lane >> 5;
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                const int row = 8 * (r >> 2) + 4 * half + (r & 3);
+                const int j = 1024 * w + 32 * row + (int)r32;
+                if (j < ca.K) sP[padk(j)] = ldexpf(cre[r] * cre[r] + cim[r] * cim[r], 2 * ex);
+            }
+            for (int j = ca.K + tid; j < fast_bins(ca.K); j += kFT) sP[padk(j)] = 0.0f;  // pads
+        });
+        return;
+    }
     comb_fast_pixel<MT, DKT>(ca, u, i_max, i_all, sf_out, snr_out, bin_out, nullptr,
                              [&](float* sP) {
         EvFused* st = (EvFused*)(sP + ca.kpad);
@@ -1311,26 +1414,40 @@ int comb_run(const float* power, int32_t n_active, const int32_t* n_dev, const d
     return DDHF_OK;
 }
 
+template <bool F16>
+static void ndft_comb_launch(const CombSetup& cs, hipStream_t s, const int32_t* row_ptr,
+                             const uint32_t* t_rel, const float* a, const int32_t* active,
+                             int32_t n_active, const GridDev& g, float* sf, float* snr_best,
+                             int32_t* bin_best) {
+    const dim3 gr((unsigned)n_active), bl(kFT);
+    if (cs.ca.M == 4 && cs.ca.dk == 3)
+        hipLaunchKernelGGL((k_ndft_comb<4, 3, F16>), gr, bl, cs.lds, s, row_ptr, t_rel, a, active,
+                           n_active, g, cs.ca, cs.i_max, cs.i_all, sf, snr_best, bin_best);
+    else if (cs.ca.M == 5 && cs.ca.dk == 3)
+        hipLaunchKernelGGL((k_ndft_comb<5, 3, F16>), gr, bl, cs.lds, s, row_ptr, t_rel, a, active,
+                           n_active, g, cs.ca, cs.i_max, cs.i_all, sf, snr_best, bin_best);
+    else
+        hipLaunchKernelGGL((k_ndft_comb<-1, -1, F16>), gr, bl, cs.lds, s, row_ptr, t_rel, a,
+                           active, n_active, g, cs.ca, cs.i_max, cs.i_all, sf, snr_best, bin_best);
+}
+
 int ndft_comb_run(const int32_t* row_ptr, const uint32_t* t_rel, const float* a,
                   const int32_t* active, int32_t n_active, const ddhf_grid_t* grid,
-                  const ddhf_params_t* prm, float* sf, float* snr_best, int32_t* bin_best,
-                  hipStream_t s) {
+                  const ddhf_params_t* prm, const ddhf_launch_t* launch, float* sf,
+                  float* snr_best, int32_t* bin_best, hipStream_t s) {
     if (!grid_ok(grid) || !comb_params_ok(grid, prm) || n_active < 0) return DDHF_EINVAL;
+    // matrix products: FP32 (kernel MFMA) or split FP16 (kernel MFMA16, the default)
+    const int kernel = launch ? launch->kernel : DDHF_KERNEL_MFMA16;
+    if (kernel != DDHF_KERNEL_MFMA && kernel != DDHF_KERNEL_MFMA16) return DDHF_EINVAL;
     const CombSetup cs = comb_setup(grid, prm);
     if (!cs.fast) return DDHF_EINVAL;
     if (n_active == 0) return DDHF_OK;
     if (!row_ptr || !t_rel || !a || !active || !sf || !snr_best || !bin_best) return DDHF_EINVAL;
     const GridDev g = grid_dev(grid);
-    const dim3 gr((unsigned)n_active), bl(kFT);
-    if (cs.ca.M == 4 && cs.ca.dk == 3)
-        hipLaunchKernelGGL((k_ndft_comb<4, 3>), gr, bl, cs.lds, s, row_ptr, t_rel, a, active,
-                           n_active, g, cs.ca, cs.i_max, cs.i_all, sf, snr_best, bin_best);
-    else if (cs.ca.M == 5 && cs.ca.dk == 3)
-        hipLaunchKernelGGL((k_ndft_comb<5, 3>), gr, bl, cs.lds, s, row_ptr, t_rel, a, active,
-                           n_active, g, cs.ca, cs.i_max, cs.i_all, sf, snr_best, bin_best);
+    if (kernel == DDHF_KERNEL_MFMA16)
+        ndft_comb_launch<true>(cs, s, row_ptr, t_rel, a, active, n_active, g, sf, snr_best, bin_best);
     else
-        hipLaunchKernelGGL((k_ndft_comb<-1, -1>), gr, bl, cs.lds, s, row_ptr, t_rel, a, active,
-                           n_active, g, cs.ca, cs.i_max, cs.i_all, sf, snr_best, bin_best);
+        ndft_comb_launch<false>(cs, s, row_ptr, t_rel, a, active, n_active, g, sf, snr_best, bin_best);
     DDHF_LAUNCH_CHECK();
     return DDHF_OK;
 }
@@ -1345,8 +1462,8 @@ extern "C" int ddhf_comb_score(const float* power, int32_t n_active, const ddhf_
 
 extern "C" int ddhf_ndft_comb(const int32_t* row_ptr, const uint32_t* t_rel, const float* a,
                               const int32_t* active, int32_t n_active, const ddhf_grid_t* grid,
-                              const ddhf_params_t* prm, float* sf, float* snr_best,
-                              int32_t* bin_best, void* stream) {
-    return ndft_comb_run(row_ptr, t_rel, a, active, n_active, grid, prm, sf, snr_best, bin_best,
-                         as_stream(stream));
+                              const ddhf_params_t* prm, const ddhf_launch_t* launch, float* sf,
+                              float* snr_best, int32_t* bin_best, void* stream) {
+    return ndft_comb_run(row_ptr, t_rel, a, active, n_active, grid, prm, launch, sf, snr_best,
+                         bin_best, as_stream(stream));
 }

@@ -163,8 +163,8 @@ int comb_run(const float* power, int32_t n_active, const int32_t* n_dev, const d
              float* snr_all, hipStream_t s);
 int ndft_comb_run(const int32_t* row_ptr, const uint32_t* t_rel, const float* a,
                   const int32_t* active, int32_t n_active, const ddhf_grid_t* grid,
-                  const ddhf_params_t* prm, float* sf, float* snr_best, int32_t* bin_best,
-                  hipStream_t s);
+                  const ddhf_params_t* prm, const ddhf_launch_t* launch, float* sf,
+                  float* snr_best, int32_t* bin_best, hipStream_t s);
 // row_ptr may be null: every listed pixel is taken to satisfy n_min.
 int detect_run(const int32_t* active, const int32_t* row_ptr, const float* sf,
                const float* snr_best, const int32_t* bin_best, int32_t n_active,

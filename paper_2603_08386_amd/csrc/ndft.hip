@@ -445,30 +445,8 @@ __global__ __launch_bounds__(64, 2) void k_ndft_mfma(const int32_t* __restrict__
 // the FP16 range; the spectrum is scaled back exactly.  Tile b's U rows are
 // tile 0's rotated b times by exp(i 2 pi 1024 D / Q).
 // ---------------------------------------------------------------------------
-typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
-typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+// FP16 operand types and the split helpers are in phase.h.
 
-// x - (float)h.lo and x - (float)h.hi for a packed FP16 pair h, one mixed-precision
-// FMA each (exact here: h holds x rounded toward zero)
-__device__ __forceinline__ float sub_f16lo(float x, uint32_t h) {
-    float d;
-    asm("v_fma_mix_f32 %0, %1, 1.0, -%2 op_sel_hi:[0,0,1]" : "=v"(d) : "v"(x), "v"(h));
-    return d;
-}
-__device__ __forceinline__ float sub_f16hi(float x, uint32_t h) {
-    float d;
-    asm("v_fma_mix_f32 %0, %1, 1.0, -%2 op_sel:[0,0,1] op_sel_hi:[0,0,1]" : "=v"(d) : "v"(x), "v"(h));
-    return d;
-}
-
-// (fp16(x), fp16(y)) toward zero and the packed remainders (fp16(x - x_h), fp16(y - y_h))
-__device__ __forceinline__ void split_pk(float x, float y, uint32_t& hi, uint32_t& lo) {
-    hi = __builtin_bit_cast(uint32_t, __builtin_amdgcn_cvt_pkrtz(x, y));
-    lo = __builtin_bit_cast(uint32_t,
-                            __builtin_amdgcn_cvt_pkrtz(sub_f16lo(x, hi), sub_f16hi(y, hi)));
-}
-
-__device__ __forceinline__ f16x8 as_f16x8(const u32x4& v) { return __builtin_bit_cast(f16x8, v); }
 
 // wavefronts per SIMD the register budget is set for: 128 accumulator
 // registers at four tiles leave room for two, 64 at two tiles for three

@@ -116,4 +116,33 @@ __device__ __forceinline__ void sincos_rev(uint32_t phi, float& s, float& c) {
     c = __builtin_amdgcn_cosf(x);
 }
 
+// ---------------------------------------------------------------------------
+// Split FP16 operands for the FP16 matrix cores: x = fp16(x) + fp16(x - fp16(x)),
+// both parts rounded toward zero.
+// ---------------------------------------------------------------------------
+typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+
+// x - (float)h.lo and x - (float)h.hi for a packed FP16 pair h, one mixed-precision
+// FMA each (exact here: h holds x rounded toward zero)
+__device__ __forceinline__ float sub_f16lo(float x, uint32_t h) {
+    float d;
+    asm("v_fma_mix_f32 %0, %1, 1.0, -%2 op_sel_hi:[0,0,1]" : "=v"(d) : "v"(x), "v"(h));
+    return d;
+}
+__device__ __forceinline__ float sub_f16hi(float x, uint32_t h) {
+    float d;
+    asm("v_fma_mix_f32 %0, %1, 1.0, -%2 op_sel:[0,0,1] op_sel_hi:[0,0,1]" : "=v"(d) : "v"(x), "v"(h));
+    return d;
+}
+
+// (fp16(x), fp16(y)) toward zero and the packed remainders (fp16(x - x_h), fp16(y - y_h))
+__device__ __forceinline__ void split_pk(float x, float y, uint32_t& hi, uint32_t& lo) {
+    hi = __builtin_bit_cast(uint32_t, __builtin_amdgcn_cvt_pkrtz(x, y));
+    lo = __builtin_bit_cast(uint32_t,
+                            __builtin_amdgcn_cvt_pkrtz(sub_f16lo(x, hi), sub_f16hi(y, hi)));
+}
+
+__device__ __forceinline__ f16x8 as_f16x8(const u32x4& v) { return __builtin_bit_cast(f16x8, v); }
+
 }  // namespace ddhf

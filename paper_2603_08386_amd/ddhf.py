@@ -208,10 +208,11 @@ def ddhf_comb_score(power, n_active, grid: Grid, prm: Params, sf, snr_best, bin_
 
 
 def ddhf_ndft_comb(row_ptr, t_rel, a, active, n_active, grid: Grid, prm: Params, sf, snr_best,
-                   bin_best, stream=None):
+                   bin_best, launch: Optional[Launch] = None, stream=None):
     rc = lib().ddhf_ndft_comb(_p(row_ptr), _p(t_rel), _p(a), _p(active), C.c_int32(n_active),
-                              C.byref(grid), C.byref(prm), _p(sf), _p(snr_best), _p(bin_best),
-                              _stream(stream))
+                              C.byref(grid), C.byref(prm),
+                              C.byref(launch) if launch is not None else None, _p(sf),
+                              _p(snr_best), _p(bin_best), _stream(stream))
     _check(rc, "ddhf_ndft_comb")
 
 
@@ -393,8 +394,12 @@ class Window:
         """Flatness and comb scores of every active pixel: the fused kernel, or
         the spectra to HBM and the comb over them."""
         if self.fused:
+            # the launch's matrix kernel; split FP16 when it names none
+            lk = self.launch
+            if lk is not None and lk.kernel not in (DDHF_KERNEL_MFMA, DDHF_KERNEL_MFMA16):
+                lk = None
             ddhf_ndft_comb(self.row_ptr, self.t_rel, self.a, self.active, self.n_active,
-                           self.grid, self.prm, self.sf, self.snr, self.bin, stream)
+                           self.grid, self.prm, self.sf, self.snr, self.bin, lk, stream)
         else:
             self.spectra(stream)
             self.score(stream)

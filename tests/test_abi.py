@@ -93,12 +93,12 @@ def test_fused_call_validates_on_the_host(lib):
     prm = Params(0.89, 1.5, 19.05, 1e-6, 4, 3, 4, 6, 147, 0)
     ok = Grid(10_000, 1000, 3991, 0, 0)
     assert lib.ddhf_ndft_comb(None, None, None, None, 0, C.byref(ok), C.byref(prm), None, None,
-                              None, None) == 0
+                              None, None, None) == 0
     too_long = Grid(10_000, 1000, 4097, 0, 0)
     assert lib.ddhf_ndft_comb(None, None, None, None, 0, C.byref(too_long), C.byref(prm), None,
-                              None, None, None) == 1
+                              None, None, None, None) == 1
     wide = Params(0.89, 1.5, 19.05, 1e-6, 32, 16, 1, 6, 147, 0)  # band of 1585 ranks
     assert lib.ddhf_ndft_comb(None, None, None, None, 0, C.byref(ok), C.byref(wide), None, None,
-                              None, None) == 1
+                              None, None, None) == 1
     assert lib.ddhf_ndft_comb(None, None, None, None, 5, C.byref(ok), C.byref(prm), None, None,
-                              None, None) == 1
+                              None, None, None) == 1

@@ -35,8 +35,9 @@ def counts_window(counts, T_w, grid, params, seed=0):
                         np.zeros((1, counts.size), bool), dict(name="counts", seed=seed))
 
 
-def fused_scores(win, order_by_cost=True):
-    g = D.window_from_synth(win, device=DEV, fused=True, order_by_cost=order_by_cost)
+def fused_scores(win, order_by_cost=True, kernel=D.DDHF_KERNEL_MFMA16):
+    g = D.window_from_synth(win, device=DEV, fused=True, order_by_cost=order_by_cost,
+                            launch=D.make_launch(kernel, 64))
     g.index()
     g.fetch_n_active()
     g.alloc_spectra()
@@ -88,13 +89,15 @@ RAGGED = [
 ]
 
 
+@pytest.mark.parametrize("kernel", [D.DDHF_KERNEL_MFMA16, D.DDHF_KERNEL_MFMA])
 @pytest.mark.parametrize("case", range(len(RAGGED)))
-def test_fused_ragged_counts_and_grids(case):
+def test_fused_ragged_counts_and_grids(case, kernel):
+    """Split-FP16 and FP32 matrix forms of the fused kernel."""
     grid, prm = RAGGED[case]
     T_w = grid.T_w_us if grid.mode == 1 else 20_000
     win = counts_window(COUNTS, T_w, grid, prm, seed=case)
-    banner(f"fused ragged K={grid.K} M={prm.M} dk={prm.dk} mode={grid.mode}")
-    g = fused_scores(win, order_by_cost=bool(case % 2))
+    banner(f"fused ragged K={grid.K} M={prm.M} dk={prm.dk} mode={grid.mode} kernel={kernel}")
+    g = fused_scores(win, order_by_cost=bool(case % 2), kernel=kernel)
     assert check_rows_against_oracle(win, g) == len(COUNTS)
 
 
@@ -197,10 +200,11 @@ def test_fused_large_sampled_and_against_two_calls():
     assert ndet >= 1
 
 
-def test_fused_deterministic():
+@pytest.mark.parametrize("kernel", [D.DDHF_KERNEL_MFMA16, D.DDHF_KERNEL_MFMA])
+def test_fused_deterministic(kernel):
     win = synth.medium_window(2)
-    g1 = fused_scores(win)
-    g2 = fused_scores(win)
+    g1 = fused_scores(win, kernel=kernel)
+    g2 = fused_scores(win, kernel=kernel)
     na = g1.n_active
     for a, b in [(g1.sf, g2.sf), (g1.snr, g2.snr), (g1.bin, g2.bin)]:
         assert torch.equal(a[:na], b[:na])
@@ -259,3 +263,34 @@ def test_scoring_selector():
     h.fetch_n_active()
     fused2, ms_s2, ms_f2 = h.select_scoring()
     assert not fused2 and ms_s2 > 0 and ms_f2 == -1.0
+
+
+def test_fused_weighted_events():
+    """Per-event weights over twelve decades and a pixel of zero weights: the
+    split-FP16 form scales each pixel's amplitudes by a power of two; scores
+    against the FP64 chain."""
+    rng = np.random.default_rng(21)
+    grid = Grid(f0=2000, df=1000, K=1500, mode=0)
+    prm = Params(M=4, dk=3, h_min=2, n_min=1)
+    base = counts_window([40, 300, 7, 90, 1200, 33], 20_000, grid, prm, seed=5)
+    w = (10.0 ** rng.uniform(-6, 6, size=base.n)).astype(np.float32)
+    w[base.x == 2] = 0.0
+    banner("fused weighted events")
+    g = D.Window(base.x, base.y, base.p, base.t, base.W, base.H, base.t0, base.T_w, grid, prm,
+                 w=w, device=DEV, fused=True, launch=D.make_launch(D.DDHF_KERNEL_MFMA16, 64))
+    g.index()
+    g.fetch_n_active()
+    g.alloc_spectra()
+    g.spectra_and_score()
+    torch.cuda.synchronize()
+    r = oracle.build_pixel_index(base.x, base.y, base.p, base.t, base.W, base.H, base.t0,
+                                 base.T_w, w=w)
+    act = oracle.active_pixels(r["row_ptr"], 1)
+    assert np.array_equal(to_np(g.active, g.n_active), act)
+    P64 = oracle.ndft_power(r["row_ptr"], r["t_rel"], r["a"], act, grid)
+    sf, snr = to_np(g.sf, g.n_active), to_np(g.snr, g.n_active)
+    for i in range(act.size):
+        sf64 = oracle.spectral_flatness(P64[i], prm.eps_rel)
+        s64, _, _ = oracle.comb_score(P64[i], grid, prm, want_all=True)
+        assert sf[i] == pytest.approx(sf64, rel=1e-3, abs=1e-6), (i, sf[i], sf64)
+        assert snr[i] == pytest.approx(s64, rel=1e-3, abs=1e-6), (i, snr[i], s64)
