@@ -106,16 +106,20 @@ def copy_calibration():
     print(json.dumps({"copy_bytes": COPY_BYTES, "launches": 3}), flush=True)
 
 
-def _pmc_mean_kib(path, counter, name_part):
+def _pmc_mean_kib(path, counter, name_part, required=True):
     """Mean per-dispatch value of one counter over the dispatches whose kernel
-    name contains name_part (rocprofv3 counter_collection.csv)."""
+    name contains name_part (rocprofv3 counter_collection.csv); (None, 0) when
+    there are none and required is False."""
     import csv
     vals = []
     with open(path) as f:
         for r in csv.DictReader(f):
-            if r["Counter_Name"] == counter and name_part in r["Kernel_Name"]:
+            parts = (name_part,) if isinstance(name_part, str) else name_part
+            if r["Counter_Name"] == counter and all(q in r["Kernel_Name"] for q in parts):
                 vals.append(float(r["Counter_Value"]))
     if not vals:
+        if not required:
+            return None, 0
         raise SystemExit(f"no {counter} rows for kernels named *{name_part}* in {path}")
     return sum(vals) / len(vals), len(vals)
 
@@ -137,10 +141,20 @@ def ndft_tag(kernel, bpl):
     return f"ndft_valu{bpl}", f"k_ndft_valu<{bpl}, 0>"
 
 
+def fused_tag(kernel):
+    """Record tag and rocprofv3 kernel-name fragment of the fused spectrum +
+    comb kernel: its split-FP16 form unless the launch asks for the FP32
+    matrix kernel."""
+    if kernel == "mfma":
+        return "ndft_comb_mfma", ("k_ndft_comb<", ", false>")
+    return "ndft_comb_mfma16", ("k_ndft_comb<", ", true>")
+
+
 def traffic_summary(args, fetch_csv, write_csv, cal_fetch_csv, cal_write_csv):
-    """HBM bytes per launch of the NDFT kernel and of the comb kernel: FETCH_SIZE
-    and WRITE_SIZE (KiB per dispatch), each scaled by bytes / reading of the
-    plain copy kernel."""
+    """HBM bytes per launch of the NDFT kernel and of the comb kernel, or of the
+    fused kernel, whichever the profiled run launched: FETCH_SIZE and
+    WRITE_SIZE (KiB per dispatch), each scaled by bytes / reading of the plain
+    copy kernel."""
     if args.kernel not in ("valu", "mfma", "mfma16"):
         raise SystemExit("--traffic-summary needs --kernel valu, mfma or mfma16")
     cf, _ = _pmc_mean_kib(cal_fetch_csv, "FETCH_SIZE", "copyBuffer")
@@ -148,11 +162,18 @@ def traffic_summary(args, fetch_csv, write_csv, cal_fetch_csv, cal_write_csv):
     fetch_scale = COPY_BYTES / (cf * 1024.0)
     write_scale = COPY_BYTES / (cw * 1024.0)
     ntag, nname = ndft_tag(args.kernel, args.bpl)
+    ftag, fname = fused_tag(args.kernel)
+    found = 0
     for prefix, name, srcs in ((ntag, nname, TRAFFIC_SOURCES["ndft"]),
-                               ("comb_fast", "k_comb_fast<", TRAFFIC_SOURCES["comb"])):
-        f, nf = _pmc_mean_kib(fetch_csv, "FETCH_SIZE", name)
-        w, nw = _pmc_mean_kib(write_csv, "WRITE_SIZE", name)
-        rec = {"kernel": name, "workload": args.workload,
+                               ("comb_fast", "k_comb_fast<", TRAFFIC_SOURCES["comb"]),
+                               (ftag, fname, TRAFFIC_SOURCES["comb"])):
+        f, nf = _pmc_mean_kib(fetch_csv, "FETCH_SIZE", name, required=False)
+        w, nw = _pmc_mean_kib(write_csv, "WRITE_SIZE", name, required=False)
+        if not nf or not nw:
+            continue
+        found += 1
+        rec = {"kernel": name if isinstance(name, str) else "*".join(name),
+               "workload": args.workload,
                "source_digest": kernel_source_digest(srcs),
                "fetch_kib_per_dispatch": f, "write_kib_per_dispatch": w, "dispatches": [nf, nw],
                "copy_fetch_kib": cf, "copy_write_kib": cw,
@@ -163,6 +184,9 @@ def traffic_summary(args, fetch_csv, write_csv, cal_fetch_csv, cal_write_csv):
             json.dump(rec, fo, indent=1)
             fo.write("\n")
         print(json.dumps(rec), flush=True)
+    if not found:
+        raise SystemExit(f"no FETCH_SIZE / WRITE_SIZE rows for {nname}, k_comb_fast or "
+                         f"{fname} in {fetch_csv}, {write_csv}")
 
 
 MI355X_CUS, MI355X_SIMDS, MI355X_XCDS = 256, 1024, 8
@@ -639,10 +663,19 @@ def main():
                  "ms": ndft_ms, "algorithmic": f"{FLOP_PER_EVENT_BIN} FLOP x {ev_bins} event-bins"}
     comb_ms = float(np.mean(stage_ms["comb"]))
     if g.fused:
-        # one kernel forms and scores the spectra: priced as the FP32 contraction
-        roof_ndft.update({"kernel": "k_ndft_comb (spectrum in LDS, flatness and comb)",
-                          "bound": "mfma", "peak": FP32_PEAK_TFLOPS,
-                          "frac": achieved_tflops / FP32_PEAK_TFLOPS, "traffic": None})
+        # one kernel forms and scores the spectra; its contraction runs in the
+        # split-FP16 form unless the launch names the FP32 matrix kernel, and is
+        # priced against that form's own peak (the time includes the comb)
+        fkind = "mfma" if kname == "mfma" else "mfma16"
+        ftag, _ = fused_tag(fkind)
+        fpeak = FP16_PEAK_TFLOPS if fkind == "mfma16" else FP32_PEAK_TFLOPS
+        ffrag = (f"k_ndft_comb<{win.params.M}, {win.params.dk}, "
+                 f"{'true' if fkind == 'mfma16' else 'false'}>")
+        roof_ndft.update({"kernel": f"{ffrag} (spectrum in LDS, flatness and comb)",
+                          "bound": "mfma", "peak": fpeak,
+                          "frac": achieved_tflops / fpeak,
+                          "traffic": load_traffic(f"{ftag}_{args.workload}",
+                                                  kernel_source_digest(TRAFFIC_SOURCES["comb"]))})
         roof_comb = None
         dominant = roof_ndft
     else:

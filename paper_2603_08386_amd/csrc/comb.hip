@@ -1075,6 +1075,18 @@ struct EvFused {
 constexpr int kFuseChunk = kFT;
 static_assert(kFuseChunk * sizeof(EvFused) <= 4 * kHistWords, "event stage fits the histograms");
 
+// Split-FP16 form: column tables of one sub-chunk of kFillSub events (one
+// thread per event and column), the B operands of V and the factors R.
+constexpr int kFillSub = kFT / 32;
+struct FillTab {
+    // [word][k][s][q] for event 4 k + q of the sub-chunk, column s; words:
+    // (Re V, -Im V) hi, lo and (Im V, Re V) hi, lo as packed FP16
+    uint32_t b[4][2][32][4];
+    float r[2][2][32][4];  // Re, Im of R[e, b] = exp(2 pi i 32 b D_e / Q), same order
+};
+constexpr int kFillEvBytes = kFuseChunk * (int)(sizeof(uint2) + 4 * sizeof(float2));
+constexpr int kFillLds = kFillEvBytes + 2 * (int)sizeof(FillTab);
+
 // phi = phiA + m F / 2^16 (mod 2^32) for bin offsets m < 2^12, from 24-bit
 // multiply-adds; error below 2^-30 revolutions.
 __device__ __forceinline__ uint32_t frac_phase12(uint32_t phiA, uint32_t q1, uint32_t q2,
@@ -1112,6 +1124,7 @@ __device__ __forceinline__ PairOps pair_operands(const EvFused& s, uint32_t mU, 
 }
 
 typedef float f32x16 __attribute__((ext_vector_type(16)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 // The split-FP16 form (F16): the same products on the FP16 matrix cores, eight
 // events per v_mfma_f32_32x32x16_f16 (lane l holds k = 8 (l / 32) .. + 7:
@@ -1142,17 +1155,33 @@ __global__ __launch_bounds__(kFT, fused_min_waves(MT, DKT)) void k_ndft_comb(con
     if constexpr (F16) {
         comb_fast_pixel<MT, DKT>(ca, u, i_max, i_all, sf_out, snr_out, bin_out, nullptr,
                                  [&](float* sP) {
-            EvFused* st = (EvFused*)(sP + ca.kpad);
+            // the fill's own layout over the dynamic LDS (the comb's arrays are
+            // written only after it): event fractions, per-wave event factors,
+            // two buffers of column tables
+            char* lds = (char*)sP;
+            uint2* sq = (uint2*)lds;                                   // [256] (q1, q2)
+            float2* sgw = (float2*)(lds + kFuseChunk * sizeof(uint2));  // [4][256] G
+            FillTab* tabs = (FillTab*)(lds + kFillEvBytes);            // [2]
             const int tid = threadIdx.x;
             const int lane = tid & (kWave - 1);
             const int w = tid / kWave;
-            const int kb = lane >> 5;                             // events 4 kb .. 4 kb + 3
-            const uint32_t r32 = (uint32_t)(lane & 31);
-            const uint32_t mU = 1024u * (uint32_t)w + 32u * r32;  // U row r32 of tile w
-            const bool live = 1024 * w < ca.K;                     // wave-uniform
-            // the pixel's amplitude scale
-            float amax = 0.0f;
-            for (int32_t e = beg + tid; e < end; e += kFT) amax = fmaxf(amax, fabsf(av[e]));
+            const int kb = lane >> 5;                // events 4 kb .. 4 kb + 3 of a sub-chunk
+            const int r32 = lane & 31;
+            const int n_live = (ca.K + 1023) >> 10;  // waves holding a bin below K
+            const bool live = w < n_live;            // wave-uniform
+            // table entry of this thread: event 4 pk + pq of a sub-chunk, column ps
+            const int pk = w >> 1, pq = lane & 3, ps = 16 * (w & 1) + (lane >> 2);
+            // the pixel's amplitude scale; each thread's first event is loaded
+            // once and kept for the first chunk's staging
+            const int32_t e_first = beg + tid;
+            uint32_t t_first = 0u;
+            float a_first = 0.0f;
+            if (e_first < end) {
+                t_first = t_rel[e_first];
+                a_first = av[e_first];
+            }
+            float amax = fabsf(a_first);
+            for (int32_t e = e_first + kFT; e < end; e += kFT) amax = fmaxf(amax, fabsf(av[e]));
             amax = wave_max(amax);
             if (lane == 0) s_amax[w] = amax;
             __syncthreads();
@@ -1164,69 +1193,123 @@ __global__ __launch_bounds__(kFT, fused_min_waves(MT, DKT)) void k_ndft_comb(con
                 if (m == 0.5f) --ex;
             }
             const float sc = ldexpf(1.0f, -ex);
-            f32x16 cre, cim;
-#pragma unroll
-            for (int r = 0; r < 16; ++r) { cre[r] = 0.0f; cim[r] = 0.0f; }
-            for (int32_t c0 = beg; c0 < end; c0 += kFuseChunk) {
-                {
-                    // stage: entries past the pixel's end carry zero weight
-                    const int32_t e = c0 + tid;
-                    EvFused s{0u, 0u, 0u, 0.0f};
-                    if (e < end) {
-                        const uint64_t t = t_rel[e];
-                        const uint32_t A = mod_q((uint64_t)g.f0 * t, g);
-                        const uint32_t D = mod_q((uint64_t)g.df * t, g);
-                        const Frac f = make_frac(A, D, g);
-                        s.phiA = f.phiA;
-                        s.q1 = (uint32_t)(f.F >> 16);
-                        s.q2 = (uint32_t)(f.F & 0xFFFFu);
-                        s.a = av[e] * sc;
+            // stage one event per thread: its D fraction and, per wave tile,
+            // G = a 2^-ex exp(2 pi i (A + 1024 w D) / Q); entries past the
+            // pixel's end are zero
+            auto stage = [&](int32_t e, uint32_t t, float a) {
+                if (e < end) {
+                    const uint32_t A = mod_q((uint64_t)g.f0 * t, g);
+                    const uint32_t D = mod_q((uint64_t)g.df * t, g);
+                    const Frac f = make_frac(A, D, g);
+                    const uint32_t q1 = (uint32_t)(f.F >> 16), q2 = (uint32_t)(f.F & 0xFFFFu);
+                    sq[tid] = make_uint2(q1, q2);
+                    a *= sc;
+                    for (int v = 0; v < n_live; ++v) {
+                        float sn, cs;
+                        sincos_rev(frac_phase12(f.phiA, q1, q2, 1024u * (uint32_t)v), sn, cs);
+                        sgw[kFuseChunk * v + tid] = make_float2(cs * a, sn * a);
                     }
-                    st[tid] = s;
+                } else {
+                    sq[tid] = make_uint2(0u, 0u);
+                    for (int v = 0; v < n_live; ++v) sgw[kFuseChunk * v + tid] = make_float2(0.0f, 0.0f);
                 }
-                __syncthreads();
-                const int ne = (end - c0) < kFuseChunk ? (end - c0) : kFuseChunk;
-                if (live) {
-                    for (int k0 = 0; k0 < ne; k0 += 8) {
-                        u32x4 brh, brl, bih, bil, ah, al;
+            };
+            f32x16 cre, cim;
+            int buf = 0;
+            // the products of the events staged in sq / sgw, kFillSub at a time
+            auto products = [&](int ne) {
+                for (int sb = 0; sb < ne; sb += kFillSub) {
+                    // column tables of kFillSub events, shared by the waves:
+                    // V[e, s] = exp(2 pi i s D / Q) as split FP16 B operands and
+                    // R[e, b] = exp(2 pi i 32 b D / Q), laid out so that each
+                    // lane's operands for its four events are 16 contiguous bytes
+                    FillTab& tb = tabs[buf];
+                    buf ^= 1;
+                    {
+                        const uint2 q = sq[sb + 4 * pk + pq];
+                        float vs, vc, rs, rc;
+                        sincos_rev(frac_phase12(0u, q.x, q.y, (uint32_t)ps), vs, vc);
+                        sincos_rev(frac_phase12(0u, q.x, q.y, 32u * (uint32_t)ps), rs, rc);
+                        // B (real part): (Re V, -Im V); B (imaginary part): (Im V, Re V)
+                        const uint32_t h =
+                            __builtin_bit_cast(uint32_t, __builtin_amdgcn_cvt_pkrtz(vc, -vs));
+                        const float dr = sub_f16lo(vc, h), di = sub_f16hi(-vs, h);
+                        tb.b[0][pk][ps][pq] = h;
+                        tb.b[1][pk][ps][pq] =
+                            __builtin_bit_cast(uint32_t, __builtin_amdgcn_cvt_pkrtz(dr, di));
+                        tb.b[2][pk][ps][pq] =
+                            __builtin_bit_cast(uint32_t, __builtin_amdgcn_cvt_pkrtz(vs, vc));
+                        tb.b[3][pk][ps][pq] =
+                            __builtin_bit_cast(uint32_t, __builtin_amdgcn_cvt_pkrtz(-di, dr));
+                        tb.r[0][pk][ps][pq] = rc;
+                        tb.r[1][pk][ps][pq] = rs;
+                    }
+                    // one barrier per sub-chunk: a wave that passes it has seen
+                    // every wave finish the previous sub-chunk's products, so the
+                    // buffer written next is free
+                    __syncthreads();
+                    if (live) {
+                        // A[b, e] = G[e, w] R[e, b] (row b = lane mod 32) in split FP16
+                        const f32x4 rc = *(const f32x4*)&tb.r[0][kb][r32][0];
+                        const f32x4 rs = *(const f32x4*)&tb.r[1][kb][r32][0];
+                        const f32x4 g01 = *(const f32x4*)&sgw[kFuseChunk * w + sb + 4 * kb];
+                        const f32x4 g23 = *(const f32x4*)&sgw[kFuseChunk * w + sb + 4 * kb + 2];
+                        u32x4 ah, al;
 #pragma unroll
                         for (int q = 0; q < 4; ++q) {
-                            const EvFused sv = st[k0 + 4 * kb + q];
-                            float vs, vc, sn, cs;
-                            sincos_rev(frac_phase12(0u, sv.q1, sv.q2, r32), vs, vc);
-                            sincos_rev(frac_phase12(sv.phiA, sv.q1, sv.q2, mU), sn, cs);
-                            // B (real part): (Re V, -Im V); B (imaginary part): (Im V, Re V)
-                            const uint32_t h =
-                                __builtin_bit_cast(uint32_t, __builtin_amdgcn_cvt_pkrtz(vc, -vs));
-                            const float dr = sub_f16lo(vc, h), di = sub_f16hi(-vs, h);
-                            brh[q] = h;
-                            brl[q] = __builtin_bit_cast(uint32_t, __builtin_amdgcn_cvt_pkrtz(dr, di));
-                            bih[q] = __builtin_bit_cast(uint32_t, __builtin_amdgcn_cvt_pkrtz(vs, vc));
-                            bil[q] = __builtin_bit_cast(uint32_t, __builtin_amdgcn_cvt_pkrtz(-di, dr));
+                            const float gx = q < 2 ? g01[2 * q] : g23[2 * q - 4];
+                            const float gy = q < 2 ? g01[2 * q + 1] : g23[2 * q - 3];
+                            const float ar = fmaf(gx, rc[q], -gy * rs[q]);
+                            const float ai = fmaf(gx, rs[q], gy * rc[q]);
                             uint32_t hq, lq;
-                            split_pk(cs * sv.a, sn * sv.a, hq, lq);
+                            split_pk(ar, ai, hq, lq);
                             ah[q] = hq;
                             al[q] = lq;
                         }
                         const f16x8 Ah = as_f16x8(ah), Al = as_f16x8(al);
-                        cre = __builtin_amdgcn_mfma_f32_32x32x16_f16(Ah, as_f16x8(brh), cre, 0, 0, 0);
-                        cim = __builtin_amdgcn_mfma_f32_32x32x16_f16(Ah, as_f16x8(bih), cim, 0, 0, 0);
-                        cre = __builtin_amdgcn_mfma_f32_32x32x16_f16(Al, as_f16x8(brh), cre, 0, 0, 0);
-                        cim = __builtin_amdgcn_mfma_f32_32x32x16_f16(Al, as_f16x8(bih), cim, 0, 0, 0);
-                        cre = __builtin_amdgcn_mfma_f32_32x32x16_f16(Ah, as_f16x8(brl), cre, 0, 0, 0);
-                        cim = __builtin_amdgcn_mfma_f32_32x32x16_f16(Ah, as_f16x8(bil), cim, 0, 0, 0);
+                        const f16x8 brh = as_f16x8(*(const u32x4*)&tb.b[0][kb][r32][0]);
+                        const f16x8 brl = as_f16x8(*(const u32x4*)&tb.b[1][kb][r32][0]);
+                        const f16x8 bih = as_f16x8(*(const u32x4*)&tb.b[2][kb][r32][0]);
+                        const f16x8 bil = as_f16x8(*(const u32x4*)&tb.b[3][kb][r32][0]);
+                        cre = __builtin_amdgcn_mfma_f32_32x32x16_f16(Ah, brh, cre, 0, 0, 0);
+                        cim = __builtin_amdgcn_mfma_f32_32x32x16_f16(Ah, bih, cim, 0, 0, 0);
+                        cre = __builtin_amdgcn_mfma_f32_32x32x16_f16(Al, brh, cre, 0, 0, 0);
+                        cim = __builtin_amdgcn_mfma_f32_32x32x16_f16(Al, bih, cim, 0, 0, 0);
+                        cre = __builtin_amdgcn_mfma_f32_32x32x16_f16(Ah, brl, cre, 0, 0, 0);
+                        cim = __builtin_amdgcn_mfma_f32_32x32x16_f16(Ah, bil, cim, 0, 0, 0);
                     }
                 }
-                __syncthreads();
-            }
-            const int half = lane >> 5;
+            };
+            // first chunk (the whole pixel below 257 events) staged before the
+            // accumulators go live
+            stage(e_first, t_first, a_first);
+            __syncthreads();
 #pragma unroll
-            for (int r = 0; r < 16; ++r) {
-                const int row = 8 * (r >> 2) + 4 * half + (r & 3);
-                const int j = 1024 * w + 32 * row + (int)r32;
-                if (j < ca.K) sP[padk(j)] = ldexpf(cre[r] * cre[r] + cim[r] * cim[r], 2 * ex);
+            for (int r = 0; r < 16; ++r) { cre[r] = 0.0f; cim[r] = 0.0f; }
+            products((end - beg) < kFuseChunk ? (end - beg) : kFuseChunk);
+            for (int32_t c0 = beg + kFuseChunk; c0 < end; c0 += kFuseChunk) {
+                __syncthreads();  // the products above read sq and sgw
+                const int32_t e = c0 + tid;
+                stage(e, e < end ? t_rel[e] : 0u, e < end ? av[e] : 0.0f);
+                __syncthreads();
+                products((end - c0) < kFuseChunk ? (end - c0) : kFuseChunk);
             }
-            for (int j = ca.K + tid; j < fast_bins(ca.K); j += kFT) sP[padk(j)] = 0.0f;  // pads
+            __syncthreads();  // the power below overwrites the tables
+            // power of the wave's tile into the padded spectrum: register r holds
+            // row 8 (r / 4) + 4 half + r % 4, column lane mod 32, bin
+            // j = 1024 w + 32 row + column, LDS index padk(j) = padk(j0) + 34 (row - 4 half)
+            // (32 row is a multiple of 16); bins from K to the tile end are pads (0)
+            if (live) {
+                const int j0 = 1024 * w + 128 * kb + r32;
+                float* dst = sP + padk(j0);
+                const bool full = 1024 * (w + 1) <= ca.K;  // wave-uniform
+#pragma unroll
+                for (int r = 0; r < 16; ++r) {
+                    const int ro = 8 * (r >> 2) + (r & 3);
+                    const float p = ldexpf(fmaf(cre[r], cre[r], cim[r] * cim[r]), 2 * ex);
+                    dst[34 * ro] = (full || j0 + 32 * ro < ca.K) ? p : 0.0f;
+                }
+            }
         });
         return;
     }
@@ -1420,14 +1503,15 @@ static void ndft_comb_launch(const CombSetup& cs, hipStream_t s, const int32_t* 
                              int32_t n_active, const GridDev& g, float* sf, float* snr_best,
                              int32_t* bin_best) {
     const dim3 gr((unsigned)n_active), bl(kFT);
+    const size_t lds = F16 && cs.lds < (size_t)kFillLds ? (size_t)kFillLds : cs.lds;
     if (cs.ca.M == 4 && cs.ca.dk == 3)
-        hipLaunchKernelGGL((k_ndft_comb<4, 3, F16>), gr, bl, cs.lds, s, row_ptr, t_rel, a, active,
+        hipLaunchKernelGGL((k_ndft_comb<4, 3, F16>), gr, bl, lds, s, row_ptr, t_rel, a, active,
                            n_active, g, cs.ca, cs.i_max, cs.i_all, sf, snr_best, bin_best);
     else if (cs.ca.M == 5 && cs.ca.dk == 3)
-        hipLaunchKernelGGL((k_ndft_comb<5, 3, F16>), gr, bl, cs.lds, s, row_ptr, t_rel, a, active,
+        hipLaunchKernelGGL((k_ndft_comb<5, 3, F16>), gr, bl, lds, s, row_ptr, t_rel, a, active,
                            n_active, g, cs.ca, cs.i_max, cs.i_all, sf, snr_best, bin_best);
     else
-        hipLaunchKernelGGL((k_ndft_comb<-1, -1, F16>), gr, bl, cs.lds, s, row_ptr, t_rel, a,
+        hipLaunchKernelGGL((k_ndft_comb<-1, -1, F16>), gr, bl, lds, s, row_ptr, t_rel, a,
                            active, n_active, g, cs.ca, cs.i_max, cs.i_all, sf, snr_best, bin_best);
 }
 
