@@ -1216,98 +1216,118 @@ __global__ __launch_bounds__(kFT, fused_min_waves(MT, DKT)) void k_ndft_comb(con
             };
             f32x16 cre, cim;
             int buf = 0;
-            // the products of the events staged in sq / sgw, kFillSub at a time
-            auto products = [&](int ne) {
-                for (int sb = 0; sb < ne; sb += kFillSub) {
-                    // column tables of kFillSub events, shared by the waves:
-                    // V[e, s] = exp(2 pi i s D / Q) as split FP16 B operands and
-                    // R[e, b] = exp(2 pi i 32 b D / Q), laid out so that each
-                    // lane's operands for its four events are 16 contiguous bytes
-                    FillTab& tb = tabs[buf];
-                    buf ^= 1;
-                    {
-                        const uint2 q = sq[sb + 4 * pk + pq];
-                        float vs, vc, rs, rc;
-                        sincos_rev(frac_phase12(0u, q.x, q.y, (uint32_t)ps), vs, vc);
-                        sincos_rev(frac_phase12(0u, q.x, q.y, 32u * (uint32_t)ps), rs, rc);
-                        // B (real part): (Re V, -Im V); B (imaginary part): (Im V, Re V)
-                        const uint32_t h =
-                            __builtin_bit_cast(uint32_t, __builtin_amdgcn_cvt_pkrtz(vc, -vs));
-                        const float dr = sub_f16lo(vc, h), di = sub_f16hi(-vs, h);
-                        tb.b[0][pk][ps][pq] = h;
-                        tb.b[1][pk][ps][pq] =
-                            __builtin_bit_cast(uint32_t, __builtin_amdgcn_cvt_pkrtz(dr, di));
-                        tb.b[2][pk][ps][pq] =
-                            __builtin_bit_cast(uint32_t, __builtin_amdgcn_cvt_pkrtz(vs, vc));
-                        tb.b[3][pk][ps][pq] =
-                            __builtin_bit_cast(uint32_t, __builtin_amdgcn_cvt_pkrtz(-di, dr));
-                        tb.r[0][pk][ps][pq] = rc;
-                        tb.r[1][pk][ps][pq] = rs;
-                    }
-                    // one barrier per sub-chunk: a wave that passes it has seen
-                    // every wave finish the previous sub-chunk's products, so the
-                    // buffer written next is free
-                    __syncthreads();
-                    if (live) {
-                        // A[b, e] = G[e, w] R[e, b] (row b = lane mod 32) in split FP16
-                        const f32x4 rc = *(const f32x4*)&tb.r[0][kb][r32][0];
-                        const f32x4 rs = *(const f32x4*)&tb.r[1][kb][r32][0];
-                        const f32x4 g01 = *(const f32x4*)&sgw[kFuseChunk * w + sb + 4 * kb];
-                        const f32x4 g23 = *(const f32x4*)&sgw[kFuseChunk * w + sb + 4 * kb + 2];
-                        u32x4 ah, al;
+            // the products of staged events sb .. sb + kFillSub - 1; ZERO (the
+            // pixel's first sub-chunk) starts the accumulators from zero
+            auto sub_chunk = [&](int sb, auto zero_tag) {
+                constexpr bool ZERO = decltype(zero_tag)::value;
+                // column tables of kFillSub events, shared by the waves:
+                // V[e, s] = exp(2 pi i s D / Q) as split FP16 B operands and
+                // R[e, b] = exp(2 pi i 32 b D / Q), laid out so that each
+                // lane's operands for its four events are 16 contiguous bytes
+                FillTab& tb = tabs[buf];
+                buf ^= 1;
+                {
+                    const uint2 q = sq[sb + 4 * pk + pq];
+                    float vs, vc, rs, rc;
+                    sincos_rev(frac_phase12(0u, q.x, q.y, (uint32_t)ps), vs, vc);
+                    sincos_rev(frac_phase12(0u, q.x, q.y, 32u * (uint32_t)ps), rs, rc);
+                    // B (real part): (Re V, -Im V); B (imaginary part): (Im V, Re V)
+                    const uint32_t h =
+                        __builtin_bit_cast(uint32_t, __builtin_amdgcn_cvt_pkrtz(vc, -vs));
+                    const float dr = sub_f16lo(vc, h), di = sub_f16hi(-vs, h);
+                    tb.b[0][pk][ps][pq] = h;
+                    tb.b[1][pk][ps][pq] =
+                        __builtin_bit_cast(uint32_t, __builtin_amdgcn_cvt_pkrtz(dr, di));
+                    tb.b[2][pk][ps][pq] =
+                        __builtin_bit_cast(uint32_t, __builtin_amdgcn_cvt_pkrtz(vs, vc));
+                    tb.b[3][pk][ps][pq] =
+                        __builtin_bit_cast(uint32_t, __builtin_amdgcn_cvt_pkrtz(-di, dr));
+                    tb.r[0][pk][ps][pq] = rc;
+                    tb.r[1][pk][ps][pq] = rs;
+                }
+                // one barrier per sub-chunk: a wave that passes it has seen
+                // every wave finish the previous sub-chunk's products, so the
+                // buffer written next is free
+                __syncthreads();
+                if (live) {
+                    // A[b, e] = G[e, w] R[e, b] (row b = lane mod 32) in split FP16
+                    const f32x4 rc = *(const f32x4*)&tb.r[0][kb][r32][0];
+                    const f32x4 rs = *(const f32x4*)&tb.r[1][kb][r32][0];
+                    const f32x4 g01 = *(const f32x4*)&sgw[kFuseChunk * w + sb + 4 * kb];
+                    const f32x4 g23 = *(const f32x4*)&sgw[kFuseChunk * w + sb + 4 * kb + 2];
+                    u32x4 ah, al;
 #pragma unroll
-                        for (int q = 0; q < 4; ++q) {
-                            const float gx = q < 2 ? g01[2 * q] : g23[2 * q - 4];
-                            const float gy = q < 2 ? g01[2 * q + 1] : g23[2 * q - 3];
-                            const float ar = fmaf(gx, rc[q], -gy * rs[q]);
-                            const float ai = fmaf(gx, rs[q], gy * rc[q]);
-                            uint32_t hq, lq;
-                            split_pk(ar, ai, hq, lq);
-                            ah[q] = hq;
-                            al[q] = lq;
-                        }
-                        const f16x8 Ah = as_f16x8(ah), Al = as_f16x8(al);
-                        const f16x8 brh = as_f16x8(*(const u32x4*)&tb.b[0][kb][r32][0]);
-                        const f16x8 brl = as_f16x8(*(const u32x4*)&tb.b[1][kb][r32][0]);
-                        const f16x8 bih = as_f16x8(*(const u32x4*)&tb.b[2][kb][r32][0]);
-                        const f16x8 bil = as_f16x8(*(const u32x4*)&tb.b[3][kb][r32][0]);
+                    for (int q = 0; q < 4; ++q) {
+                        const float gx = q < 2 ? g01[2 * q] : g23[2 * q - 4];
+                        const float gy = q < 2 ? g01[2 * q + 1] : g23[2 * q - 3];
+                        const float ar = fmaf(gx, rc[q], -gy * rs[q]);
+                        const float ai = fmaf(gx, rs[q], gy * rc[q]);
+                        uint32_t hq, lq;
+                        split_pk(ar, ai, hq, lq);
+                        ah[q] = hq;
+                        al[q] = lq;
+                    }
+                    const f16x8 Ah = as_f16x8(ah), Al = as_f16x8(al);
+                    const f16x8 brh = as_f16x8(*(const u32x4*)&tb.b[0][kb][r32][0]);
+                    const f16x8 brl = as_f16x8(*(const u32x4*)&tb.b[1][kb][r32][0]);
+                    const f16x8 bih = as_f16x8(*(const u32x4*)&tb.b[2][kb][r32][0]);
+                    const f16x8 bil = as_f16x8(*(const u32x4*)&tb.b[3][kb][r32][0]);
+                    if constexpr (ZERO) {
+                        const f32x16 z = {};
+                        cre = __builtin_amdgcn_mfma_f32_32x32x16_f16(Ah, brh, z, 0, 0, 0);
+                        cim = __builtin_amdgcn_mfma_f32_32x32x16_f16(Ah, bih, z, 0, 0, 0);
+                    } else {
                         cre = __builtin_amdgcn_mfma_f32_32x32x16_f16(Ah, brh, cre, 0, 0, 0);
                         cim = __builtin_amdgcn_mfma_f32_32x32x16_f16(Ah, bih, cim, 0, 0, 0);
-                        cre = __builtin_amdgcn_mfma_f32_32x32x16_f16(Al, brh, cre, 0, 0, 0);
-                        cim = __builtin_amdgcn_mfma_f32_32x32x16_f16(Al, bih, cim, 0, 0, 0);
-                        cre = __builtin_amdgcn_mfma_f32_32x32x16_f16(Ah, brl, cre, 0, 0, 0);
-                        cim = __builtin_amdgcn_mfma_f32_32x32x16_f16(Ah, bil, cim, 0, 0, 0);
                     }
+                    cre = __builtin_amdgcn_mfma_f32_32x32x16_f16(Al, brh, cre, 0, 0, 0);
+                    cim = __builtin_amdgcn_mfma_f32_32x32x16_f16(Al, bih, cim, 0, 0, 0);
+                    cre = __builtin_amdgcn_mfma_f32_32x32x16_f16(Ah, brl, cre, 0, 0, 0);
+                    cim = __builtin_amdgcn_mfma_f32_32x32x16_f16(Ah, bil, cim, 0, 0, 0);
                 }
             };
             // first chunk (the whole pixel below 257 events) staged before the
             // accumulators go live
             stage(e_first, t_first, a_first);
             __syncthreads();
+            const int ne0 = (end - beg) < kFuseChunk ? (end - beg) : kFuseChunk;
+            if (ne0 > 0) {
+                sub_chunk(0, std::true_type{});
+                for (int sb = kFillSub; sb < ne0; sb += kFillSub) sub_chunk(sb, std::false_type{});
+            } else {
 #pragma unroll
-            for (int r = 0; r < 16; ++r) { cre[r] = 0.0f; cim[r] = 0.0f; }
-            products((end - beg) < kFuseChunk ? (end - beg) : kFuseChunk);
+                for (int r = 0; r < 16; ++r) { cre[r] = 0.0f; cim[r] = 0.0f; }
+            }
             for (int32_t c0 = beg + kFuseChunk; c0 < end; c0 += kFuseChunk) {
                 __syncthreads();  // the products above read sq and sgw
                 const int32_t e = c0 + tid;
                 stage(e, e < end ? t_rel[e] : 0u, e < end ? av[e] : 0.0f);
                 __syncthreads();
-                products((end - c0) < kFuseChunk ? (end - c0) : kFuseChunk);
+                const int ne = (end - c0) < kFuseChunk ? (end - c0) : kFuseChunk;
+                for (int sb = 0; sb < ne; sb += kFillSub) sub_chunk(sb, std::false_type{});
             }
             __syncthreads();  // the power below overwrites the tables
             // power of the wave's tile into the padded spectrum: register r holds
             // row 8 (r / 4) + 4 half + r % 4, column lane mod 32, bin
             // j = 1024 w + 32 row + column, LDS index padk(j) = padk(j0) + 34 (row - 4 half)
-            // (32 row is a multiple of 16); bins from K to the tile end are pads (0)
+            // (32 row is a multiple of 16); bins from K to the tile end are pads (0).
+            // The spectrum stays scaled by 2^-2ex: flatness, the comb's ratios and
+            // its floor (a fraction of the mean) are unchanged by an exact
+            // power-of-two factor, so the scores are those of the unscaled power.
             if (live) {
                 const int j0 = 1024 * w + 128 * kb + r32;
                 float* dst = sP + padk(j0);
-                const bool full = 1024 * (w + 1) <= ca.K;  // wave-uniform
+                if (1024 * (w + 1) <= ca.K) {  // wave-uniform: the whole tile is below K
 #pragma unroll
-                for (int r = 0; r < 16; ++r) {
-                    const int ro = 8 * (r >> 2) + (r & 3);
-                    const float p = ldexpf(fmaf(cre[r], cre[r], cim[r] * cim[r]), 2 * ex);
-                    dst[34 * ro] = (full || j0 + 32 * ro < ca.K) ? p : 0.0f;
+                    for (int r = 0; r < 16; ++r)
+                        dst[34 * (8 * (r >> 2) + (r & 3))] = fmaf(cre[r], cre[r], cim[r] * cim[r]);
+                } else {
+#pragma unroll
+                    for (int r = 0; r < 16; ++r) {
+                        const int ro = 8 * (r >> 2) + (r & 3);
+                        const float p = fmaf(cre[r], cre[r], cim[r] * cim[r]);
+                        dst[34 * ro] = j0 + 32 * ro < ca.K ? p : 0.0f;
+                    }
                 }
             }
         });
