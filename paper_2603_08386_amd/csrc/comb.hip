@@ -358,6 +358,7 @@ static_assert(kFT * kFastItems == 4096 && (1 << kSegShift) == kFastItems, "fast 
 constexpr int kListCap = 256;
 constexpr int kInbCap = 8;         // in-band window bins kept in registers per candidate
 constexpr int kHistWords = 1280;   // 1024 packed words + pad8, rounded to 5 x 256
+constexpr int kCentreShift = 15;   // centred histogram: 256 buckets per octave
 constexpr uint8_t kCodeCand = 0xFDu, kCodeBelow = 0xFEu, kCodeAbove = 0xFFu;
 
 // one padding slot after every thread segment
@@ -506,20 +507,13 @@ __device__ __forceinline__ void comb_fast_pixel(const CombArgs& ca, int32_t u, i
     const bool live = (tid / kWave) * (kWave * kFastItems) < K;  // wave-uniform
     const bool has_pad = live && (tid / kWave + 1) * (kWave * kFastItems) > K;
     const uint32_t npad = (uint32_t)(kend - K);
-    // ---- sum and first digit (bits 20..30) ----------------------------------
+    // ---- sum ----------------------------------------------------------------
     float fsum = 0.0f;  // 16 terms per thread; the block sum is in FP64
     if (live) {
 #pragma unroll
         for (int j = 0; j < kFastItems; ++j) v[j] = sP[s0 + j];
 #pragma unroll
-        for (int j = 0; j < kFastItems; ++j) {
-            fsum += v[j];
-            // word pad8(d) = d + d / 8 of d = bits 20..29; bit 30 picks the half
-            const uint32_t b = __float_as_uint(v[j]);
-            const uint32_t w = __builtin_amdgcn_ubfe(b, 20, 10) + __builtin_amdgcn_ubfe(b, 23, 7);
-            atomicAdd(&sX[w], __builtin_amdgcn_ubfe(b, 30, 1) * 0xFFFFu + 1u);
-        }
-        if (tid == 0 && npad) atomicSub(&sX[0], npad);  // the pads' bucket-0 counts
+        for (int j = 0; j < kFastItems; ++j) fsum += v[j];
     } else {
 #pragma unroll
         for (int j = 0; j < kFastItems; ++j) v[j] = 0.0f;
@@ -527,48 +521,38 @@ __device__ __forceinline__ void comb_fast_pixel(const CombArgs& ca, int32_t u, i
     const double sum = block_sum_d<kFT>((double)fsum, red);
     const double mean = sum / (double)K;
     const float floor_v = (float)(ca.eps * mean);
-    locate_x2<1>(sX, 0, ca.b_lo, &l1lo, 0, ca.b_hi, &l1hi, scr);
-    const uint32_t d1lo = (uint32_t)l1lo.d, d1hi = (uint32_t)l1hi.d;
-    // P >= 0, so bit 31 is clear and the digit is b >> 20: the bucket range
-    // [d1lo, d1hi] is the bit-pattern range [d1lo << 20, (d1hi + 1) << 20)
-    const uint32_t b1lo = d1lo << 20, b1span = ((d1hi - d1lo + 1u) << 20) - 1u;
-#pragma unroll
-    for (int i = 0; i < kHistWords / kFT; ++i) sX[tid + i * kFT] = 0u;
-    __syncthreads();
-    // ---- log-sum (Eq. 7) and second digit (bits 10..19) ---------------------
-    // log2 terms summed pairwise in FP32 within the segment (16 terms, error
-    // a few ulps of the segment sum), then across segments in FP64
+    // ---- log-sum (Eq. 7) and a histogram centred on the mean -----------------
+    // The band of ranks [b_lo, b_hi] around the median is located in one
+    // histogram of 2048 buckets, 256 per octave of the value, centred on the
+    // mean: bucket q = clamp((b >> 15) - (bits(mean) >> 15) + 1024, 0, 2047) of
+    // the bit pattern b (P >= 0: bit order is value order), packed as the
+    // first-digit histogram below (word pad8(q mod 1024), half q / 1024).  It
+    // covers [mean / 16, 16 mean); a band reaching a clamped end bucket (a
+    // spectrum whose median is far from its mean) takes the exact two-digit
+    // select instead.  Coarser buckets put more of a wavefront's atomics on
+    // the same LDS word (fewer bank conflicts) but leave more candidates to
+    // rank; 256 per octave measured fastest on noise-like spectra.  The log2 terms are summed pairwise in FP32 within the
+    // segment (16 terms, error a few ulps of the segment sum), then across
+    // segments in FP64.
+    const int32_t cq = (int32_t)(__float_as_uint((float)mean) >> kCentreShift) - 1024;
     float lg[kFastItems];
     if (live) {
         // max(P, floor) on the bit patterns (both >= 0: integer order is value order)
         const uint32_t fb = __float_as_uint(floor_v);
 #pragma unroll
-        for (int j = 0; j < kFastItems; ++j)
-            lg[j] = __log2f(__uint_as_float(max(__float_as_uint(v[j]), fb)));
+        for (int j = 0; j < kFastItems; ++j) {
+            const uint32_t b = __float_as_uint(v[j]);
+            lg[j] = __log2f(__uint_as_float(max(b, fb)));
+            const int32_t q = min(max((int32_t)(b >> kCentreShift) - cq, 0), 2047);
+            atomicAdd(&sX[pad8(q & 1023)], q >= 1024 ? 0x10000u : 1u);
+        }
         if (has_pad) {
 #pragma unroll
             for (int j = 0; j < kFastItems; ++j) lg[j] = j < nmine ? lg[j] : 0.0f;
         }
-        // few bins fall in [d1lo, d1hi] (a few per cent): mark them branch-free,
-        // then visit the marked ones (re-read from LDS) one at a time
-        uint32_t l2m = 0u;
-#pragma unroll
-        for (int j = 0; j < kFastItems; ++j)
-            l2m |= (__float_as_uint(v[j]) - b1lo <= b1span ? 1u : 0u) << j;
-        const uint32_t b1hi = d1hi << 20;
-        while (l2m) {
-            const int j = __builtin_ctz(l2m);
-            l2m &= l2m - 1u;
-            const uint32_t b = __float_as_uint(sP[s0 + j]);
-            // word pad8(d2) of the second digit d2 = bits 10..19
-            const uint32_t w = __builtin_amdgcn_ubfe(b, 10, 10) + __builtin_amdgcn_ubfe(b, 13, 7);
-            const uint32_t inc = (b - b1lo < (1u << 20) ? 1u : 0u) + (b >= b1hi ? 1u << 16 : 0u);
-            atomicAdd(&sX[w], inc);
-        }
-        // pads (value 0: digit 0, second digit 0) counted where bucket 0 is an end bucket
-        if (tid == 0 && npad) {
-            const uint32_t take = (d1lo == 0u ? npad : 0u) + (d1hi == 0u ? npad << 16 : 0u);
-            if (take) atomicSub(&sX[0], take);
+        if (tid == 0 && npad) {  // the pads (value 0) are not part of the spectrum
+            const int32_t q0 = min(max(-cq, 0), 2047);
+            atomicSub(&sX[pad8(q0 & 1023)], q0 >= 1024 ? npad << 16 : npad);
         }
     } else {
 #pragma unroll
@@ -580,7 +564,7 @@ __device__ __forceinline__ void comb_fast_pixel(const CombArgs& ca, int32_t u, i
         for (int j = 0; j < h; ++j) lg[j] += lg[j + h];
     }
     double sl = (double)lg[0];
-    sl = block_sum_d<kFT>(sl, red);
+    sl = block_sum_d<kFT>(sl, red);  // its barrier also completes the histogram
     if (tid == 0) {
         // log2(mean) = e + log2(m), m in [0.5, 1): the FP32 logarithm of the
         // mantissa keeps the exponent difference accurate to ~1e-7
@@ -593,18 +577,71 @@ __device__ __forceinline__ void comb_fast_pixel(const CombArgs& ca, int32_t u, i
         }
         sf_out[u] = f;
     }
-    locate_x2<2>(sX, l1lo.before, ca.b_lo, &l2lo, l1hi.before, ca.b_hi, &l2hi,
-                          scr);
-    const uint32_t key_lo = (d1lo << 10) | (uint32_t)l2lo.d;
-    const uint32_t key_hi = (d1hi << 10) | (uint32_t)l2hi.d;
-    const uint32_t below_base = l2lo.before;  // values with a 21-bit key below key_lo
+    locate_x2<1>(sX, 0, ca.b_lo, &l1lo, 0, ca.b_hi, &l1hi, scr);
+    // candidates: bit patterns in [blo, bhi); below_base values lie below blo
+    uint32_t blo, bhi, below_base;
+    if (l1lo.d > 0 && l1hi.d < 2047) {  // uniform: the band is inside the centred range
+        blo = (uint32_t)(l1lo.d + cq) << kCentreShift;
+        bhi = (uint32_t)(l1hi.d + 1 + cq) << kCentreShift;
+        below_base = l1lo.before;
+    } else {
+        // exact two-digit select on the bit pattern: digit 1 = bits 20..30,
+        // digit 2 = bits 10..19 of the values inside the two end buckets
+#pragma unroll
+        for (int i = 0; i < kHistWords / kFT; ++i) sX[tid + i * kFT] = 0u;
+        __syncthreads();
+        if (live) {
+#pragma unroll
+            for (int j = 0; j < kFastItems; ++j) {
+                // word pad8(d) = d + d / 8 of d = bits 20..29; bit 30 picks the half
+                const uint32_t b = __float_as_uint(v[j]);
+                const uint32_t w = __builtin_amdgcn_ubfe(b, 20, 10) + __builtin_amdgcn_ubfe(b, 23, 7);
+                atomicAdd(&sX[w], __builtin_amdgcn_ubfe(b, 30, 1) * 0xFFFFu + 1u);
+            }
+            if (tid == 0 && npad) atomicSub(&sX[0], npad);  // the pads' bucket-0 counts
+        }
+        __syncthreads();
+        locate_x2<1>(sX, 0, ca.b_lo, &l1lo, 0, ca.b_hi, &l1hi, scr);
+        const uint32_t d1lo = (uint32_t)l1lo.d, d1hi = (uint32_t)l1hi.d;
+        // P >= 0, so bit 31 is clear and the digit is b >> 20: the bucket range
+        // [d1lo, d1hi] is the bit-pattern range [d1lo << 20, (d1hi + 1) << 20)
+        const uint32_t b1lo = d1lo << 20, b1span = ((d1hi - d1lo + 1u) << 20) - 1u;
+#pragma unroll
+        for (int i = 0; i < kHistWords / kFT; ++i) sX[tid + i * kFT] = 0u;
+        __syncthreads();
+        if (live) {
+            // few bins fall in [d1lo, d1hi]: mark them branch-free, then visit
+            // the marked ones one at a time
+            uint32_t l2m = 0u;
+#pragma unroll
+            for (int j = 0; j < kFastItems; ++j)
+                l2m |= (__float_as_uint(v[j]) - b1lo <= b1span ? 1u : 0u) << j;
+            if (has_pad) l2m &= (1u << nmine) - 1u;  // pads are counted below
+            const uint32_t b1hi = d1hi << 20;
+            while (l2m) {
+                const int j = __builtin_ctz(l2m);
+                l2m &= l2m - 1u;
+                const uint32_t b = __float_as_uint(sP[s0 + j]);
+                // word pad8(d2) of the second digit d2 = bits 10..19
+                const uint32_t w = __builtin_amdgcn_ubfe(b, 10, 10) + __builtin_amdgcn_ubfe(b, 13, 7);
+                const uint32_t inc = (b - b1lo < (1u << 20) ? 1u : 0u) + (b >= b1hi ? 1u << 16 : 0u);
+                atomicAdd(&sX[w], inc);
+            }
+        }
+        __syncthreads();
+        locate_x2<2>(sX, l1lo.before, ca.b_lo, &l2lo, l1hi.before, ca.b_hi, &l2hi, scr);
+        const uint32_t key_lo = (d1lo << 10) | (uint32_t)l2lo.d;
+        const uint32_t key_hi = (d1hi << 10) | (uint32_t)l2hi.d;
+        // the 21-bit key is b >> 10 (bit 31 clear): key < key_lo iff b < key_lo << 10,
+        // key > key_hi iff b >= (key_hi + 1) << 10
+        blo = key_lo << 10;
+        bhi = (key_hi + 1u) << 10;
+        below_base = l2lo.before;  // values with a 21-bit key below key_lo
+    }
     // ---- classify: below / above / candidate (histograms are dead now) ------
     {
         // candidates of the segment as a bit mask; one list append per wavefront
         uint32_t cmask = 0u;
-        // the 21-bit key is b >> 10 (bit 31 clear): key < key_lo iff b < key_lo << 10,
-        // key > key_hi iff b >= (key_hi + 1) << 10
-        const uint32_t blo = key_lo << 10, bhi = (key_hi + 1u) << 10;
         if (live) {
 #pragma unroll
             for (int j = 0; j < kFastItems; ++j) {
@@ -679,15 +716,14 @@ __device__ __forceinline__ void comb_fast_pixel(const CombArgs& ca, int32_t u, i
 #pragma unroll 1
         for (int j = 0; j < kFastItems; ++j) {
             if (j >= nmine) break;
-            const uint32_t kki = (__float_as_uint(v[j]) >> 10) & 0x1FFFFFu;
-            if (kki < key_lo || kki > key_hi) continue;
+            if (__float_as_uint(v[j]) - blo >= bhi - blo) continue;  // not a candidate
             const int ki = k0 + j;
             const float vi = v[j];
             uint32_t r = 0;
             for (int kj = 0; kj < K; ++kj) {
                 const float vj = sP[padk(kj)];
-                const uint32_t kk = (__float_as_uint(vj) >> 10) & 0x1FFFFFu;
-                if (kk >= key_lo && kk <= key_hi && (vj < vi || (vj == vi && kj < ki))) ++r;
+                const bool cand = __float_as_uint(vj) - blo < bhi - blo;
+                if (cand && (vj < vi || (vj == vi && kj < ki))) ++r;
             }
             set_rank(ki, vi, r);
         }

@@ -340,6 +340,28 @@ def test_comb_random_spectra_many_shapes():
         comb_compare(P, grid, prm)
 
 
+def test_comb_peaky_spectra_median_far_below_mean():
+    """Spectra whose median lies far below mean / 16 (a few bins hold nearly
+    all the power): the fast comb locates the median band with its exact
+    two-digit select there instead of the histogram centred on the mean.
+    Also a spectrum that is mostly zeros (median 0)."""
+    rng = np.random.default_rng(17)
+    for K, M, dk, hmin, f0, df in [(3991, 4, 3, 4, 10_000, 1000), (1024, 5, 3, 3, 1000, 1000),
+                                   (777, 6, 2, 2, 750, 500), (4096, 4, 3, 4, 10_000, 1000)]:
+        grid = Grid(f0=f0, df=df, K=K)
+        prm = Params(M=M, dk=dk, h_min=hmin)
+        P = rng.exponential(size=(6, K))
+        P[0, 100] = 1e6 * K                   # one bin dominates the mean
+        P[1, ::50] *= 1e4                     # 2 % of the bins far louder
+        P[2] *= 1e-3
+        P[2, 10:20] = 1e3                     # ten bins hold the power
+        P[3, rng.random(K) < 0.9] = 0.0       # mostly zeros: median 0
+        P[4, 5::37] += 1e5                    # strong comb-like spikes
+        P[5] = rng.exponential(size=K) * (rng.random(K) < 0.5) * 1e-30  # tiny, half zeros
+        banner(f"comb peaky K={K} M={M} dk={dk}")
+        comb_compare(P.astype(np.float32), grid, prm)
+
+
 def test_comb_zero_spectrum():
     grid = Grid(f0=10_000, df=500, K=400)
     sf, snr, b = run_comb(np.zeros((2, 400), np.float32), grid, Params())
