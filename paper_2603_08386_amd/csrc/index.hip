@@ -258,8 +258,12 @@ int radix_sort_pairs(uint32_t* k0, uint32_t* v0, uint32_t* k1, uint32_t* v1,
     if (n_bound <= 0 || nbits <= 0) return DDHF_OK;
     const int n_tiles = (int)((n_bound + kRadixTile - 1) / kRadixTile);
     uint32_t *ka = k0, *va = v0, *kb = k1, *vb = v1, *wa = w0, *wb = w1;
-    for (int b = bit0; b < bit0 + nbits; b += 8) {
-        const int bits = (bit0 + nbits - b) < 8 ? (bit0 + nbits - b) : 8;
+    // as few passes of at most 8 bits as the key needs, with the bits spread
+    // evenly over them (longer runs per digit than 8, 8, ..., remainder)
+    const int passes = (nbits + 7) / 8;
+    const int per = (nbits + passes - 1) / passes;
+    for (int b = bit0; b < bit0 + nbits; b += per) {
+        const int bits = (bit0 + nbits - b) < per ? (bit0 + nbits - b) : per;
         hipLaunchKernelGGL(k_radix_hist, dim3(n_tiles), dim3(kRadixThreads), 0, s, ka, n_bound,
                            n_dev, b, bits, rw.ghist, n_tiles);
         DDHF_LAUNCH_CHECK();
