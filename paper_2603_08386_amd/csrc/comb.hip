@@ -330,11 +330,13 @@ __global__ __launch_bounds__(kCombThreads) void k_comb(const float* __restrict__
 // ---------------------------------------------------------------------------
 // Fast path (K <= 4096, band <= 253 ranks).  One 256-thread workgroup per
 // pixel; thread t owns the contiguous bins [16 t, 16 t + 16).
-//   1. The row is loaded coalesced and transposed through LDS.  A two-level
-//      radix select on the top 21 bits of the FP32 bit patterns (monotone for
-//      P >= 0; 11 + 10 bits) finds the keys of ranks b_lo and b_hi; the few
-//      values sharing those keys are ranked exactly by (value, bin).
-//      Flatness (Eq. 7) rides along.
+//   1. The row is loaded coalesced and transposed through LDS.  One
+//      histogram of the FP32 bit patterns (monotone for P >= 0), 256 buckets
+//      per octave centred on the spectrum's mean, locates the buckets of ranks
+//      b_lo and b_hi; when the band reaches a clamped end bucket (median below
+//      mean / 16) a two-level radix select on the top 21 bits does instead.
+//      The few values inside the located range are ranked exactly by
+//      (value, bin).  Flatness (Eq. 7) rides along.
 //   2. Every bin gets a one-byte code: band index of its rank, or below /
 //      above the band.
 //   3. The spectrum array is overwritten by the window maxima
@@ -387,7 +389,8 @@ __host__ __device__ constexpr int fast_bins(int K) {
 
 // Histograms hold 16-bit counters, two per word (a count never exceeds
 // K <= 4096), in 1024 words padded by one per 8 (pad8):
-//   level 1: bucket d (bits 20..30 of the value) in half d >> 10 of word d & 1023;
+//   level 1: bucket d (bits 20..30 of the value, or the centred bucket q of
+//            the fast comb) in half d >> 10 of word d & 1023;
 //   level 2: bucket d (bits 10..19) of the low-end histogram in the low half and
 //            of the high-end histogram in the high half of word d.
 // locate_x2 finds, for two target ranks, the bucket holding each and the number
