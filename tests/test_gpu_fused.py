@@ -86,6 +86,10 @@ RAGGED = [
     (Grid(f0=0, df=7000, K=1000, mode=0), Params(M=6, dk=1, h_min=2, n_min=1)),
     (Grid(f0=1000, df=1000, K=5, mode=0), Params(M=1, dk=0, h_min=1, n_min=1)),
     (Grid(f0=0, df=1, K=134, mode=1, T_w_us=33_333), Params(M=4, dk=3, h_min=2, n_min=1)),
+    # K a multiple of 1024 below 4096: the live waves' tiles end exactly at K
+    # and the other waves hold no bins
+    (Grid(f0=3000, df=1000, K=2048, mode=0), Params(M=4, dk=3, h_min=2, n_min=1)),
+    (Grid(f0=2000, df=500, K=3072, mode=0), Params(M=5, dk=3, h_min=3, n_min=1)),
 ]
 
 
