@@ -150,7 +150,7 @@ def fused_tag(kernel):
     return "ndft_comb_mfma16", ("k_ndft_comb<", ", true>")
 
 
-def traffic_summary(args, fetch_csv, write_csv, cal_fetch_csv, cal_write_csv):
+def traffic_summary(args, fetch_csv, write_csv, cal_fetch_csv, cal_write_csv, out_dir=None):
     """HBM bytes per launch of the NDFT kernel and of the comb kernel, or of the
     fused kernel, whichever the profiled run launched: FETCH_SIZE and
     WRITE_SIZE (KiB per dispatch), each scaled by bytes / reading of the plain
@@ -179,7 +179,8 @@ def traffic_summary(args, fetch_csv, write_csv, cal_fetch_csv, cal_write_csv):
                "copy_fetch_kib": cf, "copy_write_kib": cw,
                "fetch_scale": fetch_scale, "write_scale": write_scale,
                "bytes_per_launch": f * 1024.0 * fetch_scale + w * 1024.0 * write_scale}
-        out = os.path.join(ROOT, "profiles", f"traffic_{prefix}_{args.workload}.json")
+        out = os.path.join(out_dir or os.path.join(ROOT, "profiles"),
+                           f"traffic_{prefix}_{args.workload}.json")
         with open(out, "w") as fo:
             json.dump(rec, fo, indent=1)
             fo.write("\n")
@@ -248,10 +249,11 @@ def kernel_source_digest(names):
     return h.hexdigest()[:16]
 
 
-def load_traffic(kernel_tag, digest):
+def load_traffic(kernel_tag, digest, profiles_dir=None):
     """HBM bytes per launch from rocprofv3 --pmc (FETCH_SIZE, WRITE_SIZE), scaled by
     a copy-kernel calibration; valid only while the kernel source is unchanged."""
-    path = os.path.join(ROOT, "profiles", f"traffic_{kernel_tag}.json")
+    path = os.path.join(profiles_dir or os.path.join(ROOT, "profiles"),
+                        f"traffic_{kernel_tag}.json")
     if not os.path.exists(path):
         return None
     with open(path) as f:
